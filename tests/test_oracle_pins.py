@@ -1,0 +1,208 @@
+"""Pins of the CPU oracle against what the mathematics fixes (no GPU).
+
+The sequential oracle (oracle/seq.py) and the dense definition (oracle/dense.py)
+are pinned to references other than themselves:
+
+* the dense definition against a textbook Kalman filter + RTS smoother in the
+  proper-prior special case, and against a QR-based least-squares solve;
+* the sequential oracle against the dense definition over a sweep of k, n, m,
+  covariance layouts and H;
+* both against closed forms (k = 0), invariants (symmetry, positive
+  definiteness, zero gradient of the objective at u_hat, residual identity) and
+  a Monte Carlo estimate of cov(u_hat).
+"""
+import numpy as np
+import pytest
+
+from oracle import dense, seq
+from paper_2502_11686_amd import gen
+from tests.kalman_rts import kf_rts
+
+
+def rel_state_err(u, ref):
+    return np.max(np.abs(u - ref)) / max(np.max(np.abs(ref)), 1e-300)
+
+
+def rel_cov_err(S, ref):
+    num = np.linalg.norm(S - ref, axis=(1, 2))
+    den = np.linalg.norm(ref, axis=(1, 2))
+    return float(np.max(num / den))
+
+
+def small(seed, k, n, m, cov="diag", H_mode="identity", F_mode="per_step"):
+    rng = np.random.default_rng(seed)
+    return gen.make_problem(rng, k, n, m, F_mode=F_mode, cov=cov, H_mode=H_mode)
+
+
+def with_prior(p, seed):
+    """Make the observation of u_0 a proper prior N(mu_0, P_0) (needs m = n)."""
+    rng = np.random.default_rng(seed)
+    n = p.n
+    p.G[0] = np.eye(n)
+    p.o[0] = rng.standard_normal(n)
+    if p.C_diag:
+        p.C[0] = gen.loguniform(rng, 0.1, 2.0, n)
+    else:
+        p.C[0] = gen.spd_dense(rng, 1, n)[0]
+    return p
+
+
+# ---------------------------------------------------------------- dense pins
+
+@pytest.mark.parametrize("cov", ["diag", "dense"])
+@pytest.mark.parametrize("k,n", [(0, 3), (1, 2), (5, 3), (12, 4)])
+def test_dense_definition_equals_kalman_rts(k, n, cov):
+    p = with_prior(small(10 + k, k, n, n, cov=cov), 99)
+    d = dense.smooth(p)
+    xs, Ps = kf_rts(p)
+    assert rel_state_err(d["u"], xs) < 1e-10
+    assert rel_cov_err(d["cov"], Ps) < 1e-9
+
+
+@pytest.mark.parametrize("k,n,m", [(0, 2, 3), (4, 3, 2), (9, 2, 1)])
+def test_dense_definition_equals_qr_lstsq(k, n, m):
+    p = small(20 + k, k, n, m, cov="dense")
+    assert rel_state_err(dense.smooth(p)["u"], dense.smooth_lstsq(p)) < 1e-10
+
+
+# ------------------------------------------------------ sequential vs dense
+
+SHAPES = [(1, 1), (2, 1), (4, 2), (3, 3), (6, 3), (4, 5)]
+KS = list(range(0, 20)) + [31, 32, 33, 63, 64, 100]
+
+
+@pytest.mark.parametrize("n,m", SHAPES)
+def test_sequential_matches_dense_sweep(n, m):
+    worst_u = worst_s = 0.0
+    for k in KS:
+        if k == 0 and m < n:
+            continue  # rank deficient: covered by test_rank_deficiency
+        for cov in ("diag", "dense"):
+            for H_mode in ("identity", "random"):
+                p = small(1000 * n + 10 * m + k, k, n, m, cov=cov, H_mode=H_mode)
+                d = dense.smooth(p)
+                o = seq.smooth(p, want_lag1=True)
+                worst_u = max(worst_u, rel_state_err(o["u"], d["u"]))
+                worst_s = max(worst_s, rel_cov_err(o["cov"], d["cov"]))
+                assert abs(o["resid2"] - d["resid2"]) <= 1e-9 * max(1.0, d["resid2"])
+                nn = p.n
+                for i in range(k):
+                    lag = d["S"][i * nn:(i + 1) * nn, (i + 1) * nn:(i + 2) * nn]
+                    assert np.linalg.norm(o["lag1"][i] - lag) <= 1e-9 * np.linalg.norm(lag) + 1e-14
+    assert worst_u < 1e-11, worst_u
+    assert worst_s < 1e-10, worst_s
+
+
+def test_sequential_matches_kalman_rts_long():
+    p = with_prior(small(7, 400, 4, 4, cov="dense"), 5)
+    o = seq.smooth(p)
+    xs, Ps = kf_rts(p)
+    assert rel_state_err(o["u"], xs) < 1e-9
+    assert rel_cov_err(o["cov"], Ps) < 1e-8
+
+
+def test_k0_closed_form():
+    rng = np.random.default_rng(3)
+    p = gen.make_problem(rng, 0, 3, 5, cov="dense")
+    L = np.linalg.cholesky(p.C[0])
+    Gw = np.linalg.solve(L, p.G[0])
+    ow = np.linalg.solve(L, p.o[0])
+    J = Gw.T @ Gw
+    u0 = np.linalg.solve(J, Gw.T @ ow)
+    o = seq.smooth(p)
+    assert rel_state_err(o["u"][0], u0) < 1e-12
+    assert rel_cov_err(o["cov"], np.linalg.inv(J)[None]) < 1e-12
+
+
+# ---------------------------------------------------------------- invariants
+
+def gradient_blocks(p, u):
+    """Blocks of A^T W (A u - b), computed step by step with K^{-1}, C^{-1}."""
+    k, n = p.k, p.n
+    g = np.zeros((k + 1, n))
+    cov = lambda x, d: np.diag(x) if d else x
+    for i in range(k + 1):
+        if p.m:
+            r = p.G[i] @ u[i] - p.o[i]
+            g[i] += p.G[i].T @ np.linalg.solve(cov(p.C[i], p.C_diag), r)
+        if i >= 1:
+            H = np.eye(n) if p.H is None else p.H[i - 1]
+            r = H @ u[i] - p.F[i - 1] @ u[i - 1] - p.c[i - 1]
+            w = np.linalg.solve(cov(p.K[i - 1], p.K_diag), r)
+            g[i] += H.T @ w
+            g[i - 1] -= p.F[i - 1].T @ w
+    return g
+
+
+@pytest.mark.parametrize("wid", [0])
+def test_invariants_full_workload0(wid):
+    p = gen.workload(wid)
+    o = seq.smooth(p)
+    S = o["cov"]
+    assert np.array_equal(S, np.swapaxes(S, 1, 2))
+    np.linalg.cholesky(S)  # raises if any block is not positive definite
+    g = gradient_blocks(p, o["u"])
+    scale = np.max(np.abs(gradient_blocks(p, np.zeros_like(o["u"]))))
+    assert np.max(np.abs(g)) < 1e-11 * scale
+
+
+def test_gradient_zero_dense_covariances():
+    p = gen.workload(1, k=2000)
+    o = seq.smooth(p, want_cov=False)
+    g = gradient_blocks(p, o["u"])
+    scale = np.max(np.abs(gradient_blocks(p, np.zeros_like(o["u"]))))
+    assert np.max(np.abs(g)) < 1e-11 * scale
+
+
+def test_monte_carlo_covariance_and_unbiasedness():
+    """cov(u_hat) over repeated noise draws matches Sigma (Section IV), and
+    E[u_hat] = u (the estimator is unbiased, Section II-A).
+
+    The model (F, G, K, C) and the true trajectory stay fixed; each draw makes
+    fresh data b = A u + e with e ~ N(0, cov(e)), i.e. c_i = u_i - F_i u_{i-1}
+    - eps_i and o_i = G_i u_i + delta_i."""
+    rng = np.random.default_rng(11)
+    p = gen.make_problem(rng, 6, 2, 1, cov="dense")
+    base = seq.smooth(p)
+    u = p.u_true
+    LK = np.linalg.cholesky(p.K)
+    LC = np.linalg.cholesky(p.C)
+    draws = 4000
+    est = np.zeros((draws, p.k + 1, p.n))
+    r = np.random.default_rng(12)
+    for t in range(draws):
+        eps = np.einsum("tij,tj->ti", LK, r.standard_normal((p.k, p.n)))
+        dlt = np.einsum("tij,tj->ti", LC, r.standard_normal((p.k + 1, p.m)))
+        q = gen.Problem(k=p.k, n=p.n, m=p.m, F=p.F, K=p.K, G=p.G, C=p.C,
+                        K_diag=False, C_diag=False, H=None,
+                        c=u[1:] - np.einsum("tij,tj->ti", p.F, u[:-1]) - eps,
+                        o=np.einsum("tij,tj->ti", p.G, u) + dlt)
+        est[t] = seq.smooth(q, want_cov=False)["u"]
+    mean = est.mean(axis=0)
+    for i in range(p.k + 1):
+        Sig = base["cov"][i]
+        d = np.linalg.solve(np.linalg.cholesky(Sig), mean[i] - u[i])
+        assert np.linalg.norm(d) * np.sqrt(draws) < 5.0  # mean within ~5 sigma
+        emp = np.cov(est[:, i, :].T)
+        assert np.linalg.norm(emp - Sig) <= 0.12 * np.linalg.norm(Sig)
+
+
+# ------------------------------------------------------------- error paths
+
+def test_rank_deficiency():
+    rng = np.random.default_rng(1)
+    p = gen.make_problem(rng, 0, 3, 2)  # k = 0 with m < n
+    assert seq.smooth(p, check=False)["status"] == seq.E_RANK
+    p = gen.make_problem(rng, 5, 2, 1)
+    p.G[:] = 0.0  # nothing observes the states
+    assert seq.smooth(p, check=False)["status"] == seq.E_RANK
+
+
+def test_not_spd():
+    rng = np.random.default_rng(2)
+    p = gen.make_problem(rng, 4, 2, 1)
+    p.K[2, 1] = -1.0
+    assert seq.smooth(p, check=False)["status"] == seq.E_NOT_SPD
+    p = gen.make_problem(rng, 4, 2, 2, cov="dense")
+    p.C[1] = -np.eye(2)
+    assert seq.smooth(p, check=False)["status"] == seq.E_NOT_SPD
