@@ -1,0 +1,144 @@
+/*
+ * ks.h -- C ABI of libks, the MI355X (gfx950) odd-even Kalman smoother.
+ *
+ * Method: Gargir & Toledo, "Parallel-in-Time Kalman Smoothing Using Orthogonal
+ * Transformations" (IPDPS 2025).  The smoother solves the generalized linear
+ * least-squares problem of Section II-A,
+ *
+ *     u_hat = argmin_u || U (A u - b) ||_2^2,     U^T U = cov(e)^{-1},
+ *
+ * for the evolution equations H_i u_i = F_i u_{i-1} + c_i + eps_i (i = 1..k,
+ * cov(eps_i) = K_i) and observation equations o_i = G_i u_i + delta_i
+ * (i = 0..k, cov(delta_i) = C_i; the paper calls C_i "L_i"), by the odd-even
+ * QR factorization U A P = Q R of Section III (recursive elimination of the
+ * even block columns with Householder transformations, one GPU launch per
+ * level), back-substitution up the levels (Section III-A), and the odd-even
+ * block SelInv of Algorithm 2 (Section IV) for the covariance blocks
+ * Sigma_i = [(R^T R)^{-1}]_{ii} = cov(u_hat_i).
+ *
+ * Layouts.  Every array argument is a DEVICE pointer to row-major, packed,
+ * step-major FP64 data (no strides, no padding):
+ *
+ *     H, F  [k][n][n]   entry t belongs to evolution step i = t + 1
+ *     c     [k][n]
+ *     K     [k][n][n] (KS_COV_DENSE) or [k][n] variances (KS_COV_DIAG)
+ *     G     [k+1][m][n]
+ *     o     [k+1][m]
+ *     C     [k+1][m][m] (KS_COV_DENSE) or [k+1][m] variances (KS_COV_DIAG)
+ *     u_out [k+1][n]         smoothed states u_hat_i
+ *     cov_out [k+1][n][n]    Sigma_i, exactly symmetric
+ *
+ * H may be NULL, meaning H_i = I.  Dense K_i and C_i are read in full (both
+ * triangles) and must be symmetric positive definite; their Cholesky factors
+ * whiten the rows (any factor V with V^T V = K^{-1} gives the same u_hat).
+ *
+ * Ownership.  The caller owns every buffer, including the device workspace
+ * given to ks_create, and the HIP stream.  The library never allocates or
+ * frees device memory.  A plan keeps the R factor in its workspace between
+ * ks_smooth and ks_covariances, so the workspace must outlive the plan.
+ *
+ * Synchrony.  ks_smooth, ks_smooth_cov and ks_covariances enqueue their
+ * kernels on the plan's stream and then synchronize on that stream before
+ * returning, so errors detected on the device come back as a status.
+ *
+ * Errors.  Functions return a ks_status and never abort, throw or print.
+ * Output contents are unspecified when the status is not KS_OK.  Argument
+ * checks run before any launch.
+ */
+#ifndef KS_H
+#define KS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    KS_OK = 0,
+    KS_E_ARG = -1,          /* bad dimension, flag, NULL pointer or unsupported n / m     */
+    KS_E_WORKSPACE = -2,    /* workspace NULL, misaligned (256 B) or smaller than needed  */
+    KS_E_NOT_SPD = -3,      /* some K_i or C_i is not symmetric positive definite          */
+    KS_E_RANK = -4,         /* U A lacks numerically full column rank (some |R_jj(p,p)|
+                               <= 64 eps max |R(q,q)|), e.g. k = 0 with m < n              */
+    KS_E_NONFINITE = -5,    /* a NaN or Inf reached the R factor                           */
+    KS_E_HIP = -6,          /* a HIP runtime call failed                                   */
+    KS_E_ORDER = -7         /* ks_covariances before a successful ks_smooth                */
+} ks_status;
+
+typedef enum { KS_FP64 = 0 } ks_precision;
+typedef enum { KS_COV_DENSE = 0, KS_COV_DIAG = 1 } ks_cov_layout;
+
+/* Problem description.  k >= 0 evolution steps (k + 1 states), state
+ * dimension n >= 1, observation dimension m >= 0 (uniform over steps). */
+typedef struct {
+    int64_t k;
+    int32_t n, m;
+    int32_t precision;   /* ks_precision                          */
+    int32_t K_layout;    /* ks_cov_layout of K                    */
+    int32_t C_layout;    /* ks_cov_layout of C                    */
+    uint32_t flags;      /* reserved, must be 0                   */
+} ks_desc;
+
+typedef struct ks_plan ks_plan;
+
+/* Exact number of device-workspace bytes a plan for *desc needs, or 0 when
+ * the description is invalid or unsupported.  Host-only; no GPU needed. */
+size_t ks_workspace_bytes(const ks_desc *desc);
+
+/* Whether this build has kernels for state dimension n and observation
+ * dimension m (1 = yes, 0 = no).  Host-only. */
+int ks_supported(int32_t n, int32_t m);
+
+/* Create a plan on a caller-owned device workspace (256-byte aligned, at
+ * least ks_workspace_bytes(desc) bytes) and a caller-owned hipStream_t
+ * (NULL = the default stream).  On success *out receives the plan. */
+ks_status ks_create(const ks_desc *desc, void *workspace, size_t ws_bytes,
+                    void *hip_stream, ks_plan **out);
+
+/* Smoothed states only (the paper's "NC" mode, Section V-D): whitening,
+ * odd-even QR (all levels) and back-substitution.  Keeps R for a later
+ * ks_covariances. */
+ks_status ks_smooth(ks_plan *plan, const double *H, const double *F,
+                    const double *c, const double *K, const double *G,
+                    const double *o, const double *C, double *u_out);
+
+/* Covariance blocks Sigma_i from the R factor of the last successful
+ * ks_smooth / ks_smooth_cov on this plan (Algorithm 2). */
+ks_status ks_covariances(ks_plan *plan, double *cov_out);
+
+/* States and covariances in one pass: the backward sweep fuses
+ * back-substitution with the SelInv level of Algorithm 2. */
+ks_status ks_smooth_cov(ks_plan *plan, const double *H, const double *F,
+                        const double *c, const double *K, const double *G,
+                        const double *o, const double *C, double *u_out,
+                        double *cov_out);
+
+/* Release the plan's host state (the workspace stays the caller's). */
+ks_status ks_destroy(ks_plan *plan);
+
+/* Static description of a status code. */
+const char *ks_status_string(ks_status s);
+
+/* Where the plan keeps the R factor inside its workspace, for inspection:
+ * block row of original column i (eliminated at level l = ctz(i+1), level
+ * column j = (i+1)/2^l - 1, even) is the record
+ *     rrow_offset + (level_rec_offset[l] + j/2) * rrow_stride    (in doubles)
+ * holding n rows of [R_ii | R_i,i+2^l | rho_i | R_i,i-2^l] (3n+1 doubles
+ * each); missing neighbour blocks are zero.  levels = L + 1 with
+ * L = floor(log2(k+1)). */
+typedef struct {
+    int32_t levels;
+    int64_t rrow_offset;          /* doubles from the workspace start */
+    int64_t rrow_stride;          /* doubles per record, n (3n + 1)   */
+    int64_t level_rec_offset[64];
+    int64_t level_columns[64];    /* N_l = floor((k+1) / 2^l)          */
+} ks_layout;
+
+ks_status ks_plan_layout(const ks_plan *plan, ks_layout *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KS_H */

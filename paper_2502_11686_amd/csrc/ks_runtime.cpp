@@ -1,0 +1,293 @@
+// ks_runtime.cpp -- host side of libks: argument checks, the level schedule,
+// the workspace layout and the launch sequence behind the C ABI of ks.h.
+//
+// Level schedule (Section III): level l has N_l = floor((k+1) / 2^l) block
+// columns; level-l column j is original column (j+1) 2^l - 1, so original
+// column i is eliminated at level ctz(i+1) and there are L = floor(log2(k+1))
+// elimination levels above the single-column base level L.  Every column is
+// eliminated exactly once, so the R factor has k+1 block rows, stored level
+// by level (ceil(N_l / 2) records at level l).
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <new>
+
+#include "ks.h"
+#include "ks_internal.h"
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    int L;
+    int64_t Nl[ks::kMaxLevels];
+    int64_t rec_off[ks::kMaxLevels];
+    int64_t sys_off[ks::kMaxLevels];   // doubles from the sys segment start (levels >= 1)
+    int64_t slot_off[ks::kMaxLevels];  // slots (pairs) before level l
+    int64_t nslots;
+    int64_t spm_first;                 // first record with stored S blocks (level 1)
+    int64_t spm_records;
+    size_t off_rrows, off_sys, off_spm, off_slots, off_flags, total;
+};
+
+bool valid_desc(const ks_desc *d) {
+    if (!d) return false;
+    if (d->k < 0 || d->k > ((int64_t)1 << 40)) return false;
+    if (d->n < 1 || d->m < 0) return false;
+    if (d->precision != KS_FP64) return false;
+    if ((d->K_layout != KS_COV_DENSE && d->K_layout != KS_COV_DIAG) ||
+        (d->C_layout != KS_COV_DENSE && d->C_layout != KS_COV_DIAG))
+        return false;
+    if (d->flags != 0) return false;
+    return true;
+}
+
+bool make_layout(const ks_desc *d, const ks::KernelSet *ks_, Layout *lo) {
+    const int64_t n = d->n;
+    const int64_t rrec = n * (3 * n + 1);
+    const int64_t srec = n * (3 * n + 2);
+    std::memset(lo, 0, sizeof(*lo));
+    int64_t N = d->k + 1;
+    int l = 0;
+    int64_t rec = 0, sys = 0, slots = 0;
+    while (true) {
+        if (l >= ks::kMaxLevels) return false;
+        lo->Nl[l] = N;
+        lo->rec_off[l] = rec;
+        lo->slot_off[l] = slots;
+        if (l >= 1) {
+            lo->sys_off[l] = sys;
+            sys += N * srec;
+        }
+        rec += (N + 1) / 2;
+        const int64_t units = N == 1 ? 1 : N / 2;
+        slots += N == 1 ? 1 : (units + ks_->units_per_block_fwd - 1) / ks_->units_per_block_fwd;
+        if (N == 1) break;
+        N /= 2;
+        ++l;
+    }
+    lo->L = l;
+    lo->nslots = slots;
+    lo->spm_first = lo->L >= 1 ? lo->rec_off[1] : rec;
+    lo->spm_records = rec - lo->spm_first;
+    size_t off = 0;
+    lo->off_rrows = off;
+    off = align_up(off + sizeof(double) * (size_t)rec * rrec);
+    lo->off_sys = off;
+    off = align_up(off + sizeof(double) * (size_t)sys);
+    lo->off_spm = off;
+    off = align_up(off + sizeof(double) * (size_t)lo->spm_records * 2 * n * n);
+    lo->off_slots = off;
+    off = align_up(off + sizeof(double) * 2 * (size_t)slots);
+    lo->off_flags = off;
+    off = align_up(off + 64);
+    lo->total = off;
+    return true;
+}
+
+}  // namespace
+
+struct ks_plan {
+    ks_desc d;
+    hipStream_t stream;
+    char *ws;
+    const ks::KernelSet *kset;
+    Layout lo;
+    bool smoothed;
+    unsigned host_flags;   // status word copied back after each call
+};
+
+namespace {
+
+ks_status hip_err(hipError_t e) { return e == hipSuccess ? KS_OK : KS_E_HIP; }
+
+double *seg_d(ks_plan *p, size_t off) { return reinterpret_cast<double *>(p->ws + off); }
+
+void enqueue_forward(ks_plan *p, const double *H, const double *F, const double *c,
+                     const double *K, const double *G, const double *o, const double *C) {
+    const Layout &lo = p->lo;
+    const int64_t n = p->d.n;
+    const int64_t rrec = n * (3 * n + 1);
+    double *rrows = seg_d(p, lo.off_rrows);
+    double *sys = seg_d(p, lo.off_sys);
+    double *slots = seg_d(p, lo.off_slots);
+    unsigned *flags = reinterpret_cast<unsigned *>(p->ws + lo.off_flags);
+    ks::launch_clear_flags(flags, p->stream);
+    for (int l = 0; l <= lo.L; ++l) {
+        ks::FwdArgs a{};
+        a.k = p->d.k;
+        a.Nl = lo.Nl[l];
+        a.units = lo.Nl[l] == 1 ? 1 : lo.Nl[l] / 2;
+        a.level = l;
+        a.m = p->d.m;
+        a.K_diag = p->d.K_layout == KS_COV_DIAG;
+        a.C_diag = p->d.C_layout == KS_COV_DIAG;
+        a.H = H; a.F = F; a.c = c; a.K = K; a.G = G; a.o = o; a.C = C;
+        a.sys_in = l >= 1 ? sys + lo.sys_off[l] : nullptr;
+        a.sys_out = l < lo.L ? sys + lo.sys_off[l + 1] : nullptr;
+        a.rrows = rrows + lo.rec_off[l] * rrec;
+        a.slots = slots + 2 * lo.slot_off[l];
+        a.flags = flags;
+        if (lo.Nl[l] == 1)
+            (l == 0 ? p->kset->base_raw : p->kset->base)(a, p->stream);
+        else
+            (l == 0 ? p->kset->fwd_raw : p->kset->fwd)(a, p->stream);
+    }
+    ks::launch_status(slots, lo.nslots, flags, p->stream);
+}
+
+void enqueue_backward(ks_plan *p, double *u_out, double *cov_out) {
+    const Layout &lo = p->lo;
+    ks::BwdArgs b{};
+    b.k = p->d.k;
+    b.rrows_all = seg_d(p, lo.off_rrows);
+    b.u_in = u_out;
+    b.u_out = u_out;
+    b.cov = cov_out;
+    b.spm = seg_d(p, lo.off_spm);
+    b.spm_first = lo.spm_first;
+    for (int l = 0; l <= lo.L; ++l) b.rec_off[l] = lo.rec_off[l];
+    for (int l = lo.L; l >= 0; --l) {
+        b.level = l;
+        b.units = (lo.Nl[l] + 1) / 2;
+        b.store_s = cov_out && l >= 1;
+        if (u_out && cov_out)
+            p->kset->bwd_both(b, p->stream);
+        else if (u_out)
+            p->kset->bwd_y(b, p->stream);
+        else
+            p->kset->bwd_cov(b, p->stream);
+    }
+}
+
+ks_status finish(ks_plan *p) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return KS_E_HIP;
+    const unsigned *flags = reinterpret_cast<const unsigned *>(p->ws + p->lo.off_flags);
+    e = hipMemcpyAsync(&p->host_flags, flags, sizeof(unsigned), hipMemcpyDeviceToHost, p->stream);
+    if (e != hipSuccess) return KS_E_HIP;
+    e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return KS_E_HIP;
+    const unsigned f = p->host_flags;
+    if (f & ks::FLAG_NOT_SPD) return KS_E_NOT_SPD;
+    if (f & ks::FLAG_NONFINITE) return KS_E_NONFINITE;
+    if (f & ks::FLAG_RANK) return KS_E_RANK;
+    return KS_OK;
+}
+
+bool inputs_ok(const ks_plan *p, const double *F, const double *c, const double *K,
+               const double *G, const double *o, const double *C) {
+    if (p->d.k > 0 && (!F || !c || !K)) return false;
+    if (p->d.m > 0 && (!G || !o || !C)) return false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t ks_workspace_bytes(const ks_desc *desc) {
+    if (!valid_desc(desc)) return 0;
+    const ks::KernelSet *kset = ks::find_kernels(desc->n, desc->m);
+    if (!kset) return 0;
+    Layout lo;
+    if (!make_layout(desc, kset, &lo)) return 0;
+    return lo.total;
+}
+
+int ks_supported(int32_t n, int32_t m) { return ks::find_kernels(n, m) != nullptr; }
+
+ks_status ks_create(const ks_desc *desc, void *workspace, size_t ws_bytes, void *hip_stream,
+                    ks_plan **out) {
+    if (!out) return KS_E_ARG;
+    *out = nullptr;
+    if (!valid_desc(desc)) return KS_E_ARG;
+    const ks::KernelSet *kset = ks::find_kernels(desc->n, desc->m);
+    if (!kset) return KS_E_ARG;
+    Layout lo;
+    if (!make_layout(desc, kset, &lo)) return KS_E_ARG;
+    if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0 || ws_bytes < lo.total)
+        return KS_E_WORKSPACE;
+    ks_plan *p = new (std::nothrow) ks_plan;
+    if (!p) return KS_E_ARG;
+    p->d = *desc;
+    p->stream = static_cast<hipStream_t>(hip_stream);
+    p->ws = static_cast<char *>(workspace);
+    p->kset = kset;
+    p->lo = lo;
+    p->smoothed = false;
+    p->host_flags = 0;
+    *out = p;
+    return KS_OK;
+}
+
+ks_status ks_smooth(ks_plan *p, const double *H, const double *F, const double *c,
+                    const double *K, const double *G, const double *o, const double *C,
+                    double *u_out) {
+    if (!p || !u_out || !inputs_ok(p, F, c, K, G, o, C)) return KS_E_ARG;
+    p->smoothed = false;
+    enqueue_forward(p, H, F, c, K, G, o, C);
+    enqueue_backward(p, u_out, nullptr);
+    ks_status s = finish(p);
+    p->smoothed = s == KS_OK;
+    return s;
+}
+
+ks_status ks_smooth_cov(ks_plan *p, const double *H, const double *F, const double *c,
+                        const double *K, const double *G, const double *o, const double *C,
+                        double *u_out, double *cov_out) {
+    if (!p || !u_out || !cov_out || !inputs_ok(p, F, c, K, G, o, C)) return KS_E_ARG;
+    p->smoothed = false;
+    enqueue_forward(p, H, F, c, K, G, o, C);
+    enqueue_backward(p, u_out, cov_out);
+    ks_status s = finish(p);
+    p->smoothed = s == KS_OK;
+    return s;
+}
+
+ks_status ks_covariances(ks_plan *p, double *cov_out) {
+    if (!p || !cov_out) return KS_E_ARG;
+    if (!p->smoothed) return KS_E_ORDER;
+    enqueue_backward(p, nullptr, cov_out);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return KS_E_HIP;
+    return hip_err(hipStreamSynchronize(p->stream));
+}
+
+ks_status ks_destroy(ks_plan *p) {
+    if (!p) return KS_E_ARG;
+    delete p;
+    return KS_OK;
+}
+
+const char *ks_status_string(ks_status s) {
+    switch (s) {
+    case KS_OK: return "ok";
+    case KS_E_ARG: return "invalid argument or unsupported dimensions";
+    case KS_E_WORKSPACE: return "workspace missing, misaligned or too small";
+    case KS_E_NOT_SPD: return "a covariance matrix is not symmetric positive definite";
+    case KS_E_RANK: return "U A lacks full column rank";
+    case KS_E_NONFINITE: return "non-finite value in the R factor";
+    case KS_E_HIP: return "HIP runtime error";
+    case KS_E_ORDER: return "ks_covariances called before a successful ks_smooth";
+    }
+    return "unknown status";
+}
+
+ks_status ks_plan_layout(const ks_plan *p, ks_layout *out) {
+    if (!p || !out) return KS_E_ARG;
+    std::memset(out, 0, sizeof(*out));
+    out->levels = p->lo.L + 1;
+    out->rrow_offset = (int64_t)(p->lo.off_rrows / sizeof(double));
+    out->rrow_stride = (int64_t)p->d.n * (3 * p->d.n + 1);
+    for (int l = 0; l <= p->lo.L; ++l) {
+        out->level_rec_offset[l] = p->lo.rec_off[l];
+        out->level_columns[l] = p->lo.Nl[l];
+    }
+    return KS_OK;
+}
+
+}  // extern "C"

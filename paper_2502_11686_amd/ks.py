@@ -1,0 +1,236 @@
+"""Python binding of libks (C ABI in include/ks.h): argument marshalling only.
+
+Every step of the smoother runs in the HIP kernels of libks.so; this module
+checks tensor shapes, dtypes and devices, allocates outputs and the workspace
+with torch (device memory and streams are the only things torch provides), and
+calls the C entry points with raw device pointers.  There is no CPU fallback:
+if the library is missing, every entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libks.so")
+
+KS_OK, KS_E_ARG, KS_E_WORKSPACE, KS_E_NOT_SPD, KS_E_RANK = 0, -1, -2, -3, -4
+KS_E_NONFINITE, KS_E_HIP, KS_E_ORDER = -5, -6, -7
+KS_FP64 = 0
+KS_COV_DENSE, KS_COV_DIAG = 0, 1
+
+SYMBOLS = ("ks_workspace_bytes", "ks_supported", "ks_create", "ks_smooth", "ks_covariances",
+           "ks_smooth_cov", "ks_destroy", "ks_status_string", "ks_plan_layout")
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int64), ("n", ctypes.c_int32), ("m", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("K_layout", ctypes.c_int32),
+                ("C_layout", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class Layout(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int32), ("rrow_offset", ctypes.c_int64),
+                ("rrow_stride", ctypes.c_int64), ("level_rec_offset", ctypes.c_int64 * 64),
+                ("level_columns", ctypes.c_int64 * 64)]
+
+
+class KsError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        msg = lib().ks_status_string(status).decode()
+        super().__init__(f"{what}: {msg} (status {status})" if what else msg)
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libks.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "(the smoother has no CPU fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, dp = ctypes.c_void_p, ctypes.c_void_p
+    L.ks_workspace_bytes.restype = ctypes.c_size_t
+    L.ks_workspace_bytes.argtypes = [ctypes.POINTER(Desc)]
+    L.ks_supported.restype = ctypes.c_int
+    L.ks_supported.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    L.ks_create.restype = ctypes.c_int
+    L.ks_create.argtypes = [ctypes.POINTER(Desc), vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    L.ks_smooth.restype = ctypes.c_int
+    L.ks_smooth.argtypes = [vp] + [dp] * 8
+    L.ks_smooth_cov.restype = ctypes.c_int
+    L.ks_smooth_cov.argtypes = [vp] + [dp] * 9
+    L.ks_covariances.restype = ctypes.c_int
+    L.ks_covariances.argtypes = [vp, dp]
+    L.ks_destroy.restype = ctypes.c_int
+    L.ks_destroy.argtypes = [vp]
+    L.ks_status_string.restype = ctypes.c_char_p
+    L.ks_status_string.argtypes = [ctypes.c_int]
+    L.ks_plan_layout.restype = ctypes.c_int
+    L.ks_plan_layout.argtypes = [vp, ctypes.POINTER(Layout)]
+    _lib = L
+    return L
+
+
+def make_desc(k: int, n: int, m: int, K_diag: bool, C_diag: bool) -> Desc:
+    return Desc(k=int(k), n=int(n), m=int(m), precision=KS_FP64,
+                K_layout=KS_COV_DIAG if K_diag else KS_COV_DENSE,
+                C_layout=KS_COV_DIAG if C_diag else KS_COV_DENSE, flags=0)
+
+
+def workspace_bytes(k: int, n: int, m: int, K_diag: bool, C_diag: bool) -> int:
+    d = make_desc(k, n, m, K_diag, C_diag)
+    return int(lib().ks_workspace_bytes(ctypes.byref(d)))
+
+
+def supported(n: int, m: int) -> bool:
+    return bool(lib().ks_supported(int(n), int(m)))
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _check(t: Optional[torch.Tensor], name: str, shape, device, allow_none=False):
+    if t is None:
+        if allow_none:
+            return
+        raise ValueError(f"{name} is required")
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64, got {t.dtype}")
+    if t.device != device:
+        raise ValueError(f"{name} must be on {device}, got {t.device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+
+
+class Plan:
+    """A smoothing plan for one problem shape, owning its device workspace."""
+
+    def __init__(self, k: int, n: int, m: int, K_diag: bool, C_diag: bool,
+                 device: Optional[torch.device] = None, stream: Optional[torch.cuda.Stream] = None):
+        self.k, self.n, self.m = int(k), int(n), int(m)
+        self.K_diag, self.C_diag = bool(K_diag), bool(C_diag)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._desc = make_desc(k, n, m, K_diag, C_diag)
+        L = lib()
+        nbytes = int(L.ks_workspace_bytes(ctypes.byref(self._desc)))
+        if nbytes == 0:
+            raise KsError(KS_E_ARG, f"unsupported problem (k={k}, n={n}, m={m})")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        self.ws_bytes = nbytes
+        h = ctypes.c_void_p()
+        st = L.ks_create(ctypes.byref(self._desc), ctypes.c_void_p(self._ws_ptr), nbytes,
+                         ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if st != KS_OK:
+            raise KsError(st, "ks_create")
+        self._h = h
+
+    # ---------------------------------------------------------------- checks
+    def _check_inputs(self, H, F, c, K, G, o, C):
+        k, n, m, dev = self.k, self.n, self.m, self.device
+        _check(H, "H", (k, n, n), dev, allow_none=True)
+        _check(F, "F", (k, n, n), dev)
+        _check(c, "c", (k, n), dev)
+        _check(K, "K", (k, n) if self.K_diag else (k, n, n), dev)
+        _check(G, "G", (k + 1, m, n), dev)
+        _check(o, "o", (k + 1, m), dev)
+        _check(C, "C", (k + 1, m) if self.C_diag else (k + 1, m, m), dev)
+
+    def _out(self, t, shape, name):
+        if t is None:
+            return torch.empty(shape, dtype=torch.float64, device=self.device)
+        _check(t, name, shape, self.device)
+        return t
+
+    # ------------------------------------------------------------ entry points
+    def smooth(self, H, F, c, K, G, o, C, u_out=None):
+        """States only (no covariances); the R factor stays in the workspace."""
+        self._check_inputs(H, F, c, K, G, o, C)
+        u = self._out(u_out, (self.k + 1, self.n), "u_out")
+        st = lib().ks_smooth(self._h, _ptr(H), _ptr(F), _ptr(c), _ptr(K), _ptr(G), _ptr(o),
+                             _ptr(C), _ptr(u))
+        if st != KS_OK:
+            raise KsError(st, "ks_smooth")
+        return u
+
+    def smooth_cov(self, H, F, c, K, G, o, C, u_out=None, cov_out=None):
+        """States and covariance blocks in one pass."""
+        self._check_inputs(H, F, c, K, G, o, C)
+        u = self._out(u_out, (self.k + 1, self.n), "u_out")
+        cov = self._out(cov_out, (self.k + 1, self.n, self.n), "cov_out")
+        st = lib().ks_smooth_cov(self._h, _ptr(H), _ptr(F), _ptr(c), _ptr(K), _ptr(G), _ptr(o),
+                                 _ptr(C), _ptr(u), _ptr(cov))
+        if st != KS_OK:
+            raise KsError(st, "ks_smooth_cov")
+        return u, cov
+
+    def covariances(self, cov_out=None):
+        """Covariance blocks from the R factor of the last successful smooth."""
+        cov = self._out(cov_out, (self.k + 1, self.n, self.n), "cov_out")
+        st = lib().ks_covariances(self._h, _ptr(cov))
+        if st != KS_OK:
+            raise KsError(st, "ks_covariances")
+        return cov
+
+    def layout(self) -> dict:
+        lay = Layout()
+        st = lib().ks_plan_layout(self._h, ctypes.byref(lay))
+        if st != KS_OK:
+            raise KsError(st, "ks_plan_layout")
+        lv = lay.levels
+        return dict(levels=lv, rrow_offset=lay.rrow_offset, rrow_stride=lay.rrow_stride,
+                    level_rec_offset=list(lay.level_rec_offset[:lv]),
+                    level_columns=list(lay.level_columns[:lv]))
+
+    def r_records(self) -> torch.Tensor:
+        """The R-factor records in the workspace, as a [(k+1), n, 3n+1] view."""
+        lay = self.layout()
+        n = self.n
+        off = self._ws_ptr - self.workspace.data_ptr()
+        words = self.workspace[off:off + self.ws_bytes].view(torch.float64)
+        start = lay["rrow_offset"]
+        return words[start:start + (self.k + 1) * lay["rrow_stride"]].view(self.k + 1, n, 3 * n + 1)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().ks_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def to_device(p, device="cuda"):
+    """Problem arrays (numpy, from gen) as float64 device tensors in ABI order."""
+    def t(a):
+        return None if a is None else torch.from_numpy(a).to(device=device, dtype=torch.float64).contiguous()
+    return tuple(t(a) for a in (p.H, p.F, p.c, p.K, p.G, p.o, p.C))
+
+
+def smooth_problem(p, want_cov: bool = True, device="cuda"):
+    """Convenience: smooth a generated problem; returns device tensors (u, cov)."""
+    args = to_device(p, device)
+    plan = Plan(p.k, p.n, p.m, p.K_diag, p.C_diag, device=device)
+    try:
+        if want_cov:
+            return plan.smooth_cov(*args)
+        return plan.smooth(*args), None
+    finally:
+        plan.close()

@@ -1,0 +1,82 @@
+"""Host-side checks of libks: it loads, exports every symbol of include/ks.h, and
+its planner (argument checks, level schedule, workspace layout) behaves, all
+without a GPU (no compute calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2502_11686_amd import ks
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    txt = open(os.path.join(ROOT, "include", "ks.h")).read()
+    return sorted(set(re.findall(r"\b(ks_[a-z_]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol():
+    L = ks.lib()
+    decl = header_symbols()
+    assert decl, "no declarations found"
+    for name in decl:
+        assert hasattr(L, name), name
+    assert sorted(ks.SYMBOLS) == decl
+
+
+def test_status_strings():
+    L = ks.lib()
+    for st in range(-7, 1):
+        assert L.ks_status_string(st)
+
+
+@pytest.mark.parametrize("k,n,m", [(0, 2, 2), (1000, 4, 2), (100000, 6, 3), (77, 3, 6)])
+def test_layout_matches_level_schedule(k, n, m):
+    """Level l has floor((k+1)/2^l) columns, ceil(N_l/2) R records; every column
+    is eliminated exactly once at level ctz(i+1)."""
+    plan = ks.Plan.__new__(ks.Plan)  # host-only: create a plan on a fake aligned address
+    d = ks.make_desc(k, n, m, True, True)
+    nbytes = ks.workspace_bytes(k, n, m, True, True)
+    assert nbytes > 0 and nbytes % 256 == 0
+    h = ctypes.c_void_p()
+    st = ks.lib().ks_create(ctypes.byref(d), ctypes.c_void_p(1 << 20), nbytes, None, ctypes.byref(h))
+    assert st == ks.KS_OK
+    lay = ks.Layout()
+    assert ks.lib().ks_plan_layout(h, ctypes.byref(lay)) == ks.KS_OK
+    ks.lib().ks_destroy(h)
+    N, l, rec = k + 1, 0, 0
+    while True:
+        assert lay.level_columns[l] == N
+        assert lay.level_rec_offset[l] == rec
+        rec += (N + 1) // 2
+        if N == 1:
+            break
+        N //= 2
+        l += 1
+    assert lay.levels == l + 1 == (k + 1).bit_length()
+    assert rec == k + 1
+    assert lay.rrow_stride == n * (3 * n + 1)
+    # brute force: elimination level of each column is ctz(i+1)
+    lv = [((i + 1) & -(i + 1)).bit_length() - 1 for i in range(min(k + 1, 5000))]
+    for i, li in enumerate(lv):
+        j = (i + 1) // (1 << li) - 1
+        assert j % 2 == 0 and j < lay.level_columns[li]
+
+
+def test_argument_errors():
+    L = ks.lib()
+    h = ctypes.c_void_p()
+    bad = [ks.make_desc(-1, 2, 1, True, True), ks.make_desc(10, 0, 1, True, True),
+           ks.make_desc(10, 2, -1, True, True), ks.make_desc(10, 5, 3, True, True)]
+    for d in bad:
+        assert L.ks_workspace_bytes(ctypes.byref(d)) == 0
+        assert L.ks_create(ctypes.byref(d), ctypes.c_void_p(1 << 20), 1 << 30, None, ctypes.byref(h)) == ks.KS_E_ARG
+    d = ks.make_desc(10, 2, 1, True, True)
+    nb = ks.workspace_bytes(10, 2, 1, True, True)
+    assert L.ks_create(ctypes.byref(d), None, nb, None, ctypes.byref(h)) == ks.KS_E_WORKSPACE
+    assert L.ks_create(ctypes.byref(d), ctypes.c_void_p((1 << 20) + 8), nb, None, ctypes.byref(h)) == ks.KS_E_WORKSPACE
+    assert L.ks_create(ctypes.byref(d), ctypes.c_void_p(1 << 20), nb - 256, None, ctypes.byref(h)) == ks.KS_E_WORKSPACE
+    assert L.ks_covariances(None, None) == ks.KS_E_ARG
+    assert L.ks_destroy(None) == ks.KS_E_ARG
