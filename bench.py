@@ -1,0 +1,187 @@
+"""Throughput benchmark of the odd-even Kalman smoother on one MI355X.
+
+One step = one full smoothing pass (states and covariance blocks) of the
+single-trajectory workload: n = 6, m = 3, k = 100000 (100001 states), per-step
+F_i, dense SPD K_i and C_i, synthetic seeded data already resident in HBM.
+Prints one JSON line:
+  value        smoothed time steps per second (k+1 per step / wall time)
+  roofline     the level-0 forward kernel (loads raw inputs, whitens, first
+               elimination level): algorithmic bytes per launch / its average
+               duration from hipEvents recorded on its own stream
+  cpu_baseline the CPU oracle (sequential FP64 Paige-Saunders + Algorithm 1,
+               single thread) timed on this host on a bounded sample
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fwd_level0_n6_k100000.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2502_11686_amd", "csrc", "ks_kernels.hip")
+
+
+def level0_forward_bytes(p) -> int:
+    """Algorithmic HBM bytes of the level-0 forward launch.
+
+    Reads every raw input once (F, c, K for k steps, G, o, C for k+1 steps; H is
+    the identity and not read) and writes ceil((k+1)/2) R-factor records of
+    n(3n+1) doubles and floor((k+1)/2) reduced-system columns of n(3n+2)
+    doubles."""
+    k, n, m = p.k, p.n, p.m
+    kk = n if p.K_diag else n * n
+    cc = m if p.C_diag else m * m
+    reads = k * (n * n + n + kk) + (k + 1) * (m * n + m + cc)
+    if p.H is not None:
+        reads += k * n * n
+    writes = ((k + 2) // 2) * n * (3 * n + 1) + ((k + 1) // 2) * n * (3 * n + 2)
+    return 8 * (reads + writes)
+
+
+def kernel_source_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(per_launch_algo: int):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when it is missing or was taken on a different kernel source."""
+    try:
+        d = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(p, budget_s: float = 10.0):
+    from oracle import seq
+    seq.load()
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        seq.smooth(p)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    return dict(value=(p.k + 1) * reps / el, unit="steps/s", cores=1, kind="oracle",
+                sample=f"the full workload (k={p.k}, n={p.n}, m={p.m}) solved {reps} times "
+                       f"in {el:.1f} s, one thread, C FP64")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--k", type=int, default=100000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(independent problems shard with no communication; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2502_11686_amd import gen, ks
+
+    p = gen.workload(1, k=args.k)
+    dev = torch.device("cuda", 0)
+    tens = ks.to_device(p, dev)
+    plan = ks.Plan(p.k, p.n, p.m, p.K_diag, p.C_diag, device=dev)
+    u = torch.empty((p.k + 1, p.n), dtype=torch.float64, device=dev)
+    S = torch.empty((p.k + 1, p.n, p.n), dtype=torch.float64, device=dev)
+    for _ in range(args.warmup):
+        plan.smooth_cov(*tens, u_out=u, cov_out=S)
+
+    # timed region: K full passes, each a synchronous library call
+    plan.time_kernels(ks.KS_TIME_FWD_LEVEL0)
+    lat = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        plan.smooth_cov(*tens, u_out=u, cov_out=S)
+        lat.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    k_ms, k_cnt = plan.kernel_time()
+
+    # states-only (NC) rate and the phase split, outside the timed region
+    plan.time_kernels(ks.KS_TIME_OFF)
+    nc_steps = max(10, args.steps // 4)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(nc_steps):
+        plan.smooth(*tens, u_out=u)
+    torch.cuda.synchronize()
+    nc_el = time.perf_counter() - t1
+    phases = {}
+    for name, kind in (("forward_all", ks.KS_TIME_FWD_ALL), ("backward_all", ks.KS_TIME_BWD_ALL),
+                       ("backward_level0", ks.KS_TIME_BWD_LEVEL0)):
+        plan.time_kernels(kind)
+        for _ in range(10):
+            plan.smooth_cov(*tens, u_out=u, cov_out=S)
+        ms, cnt = plan.kernel_time()
+        phases[name] = round(ms / max(cnt, 1), 4)
+    plan.time_kernels(ks.KS_TIME_OFF)
+
+    err = None
+    if not args.no_check:
+        from oracle import seq
+        ref = seq.smooth(p)
+        plan.smooth_cov(*tens, u_out=u, cov_out=S)
+        uu, SS = u.cpu().numpy(), S.cpu().numpy()
+        err = dict(state=float(np.max(np.abs(uu - ref["u"])) / np.max(np.abs(ref["u"]))),
+                   cov=float(np.max(np.linalg.norm(SS - ref["cov"], axis=(1, 2)) /
+                                    np.linalg.norm(ref["cov"], axis=(1, 2)))))
+
+    algo = level0_forward_bytes(p)
+    avg_s = (k_ms / max(k_cnt, 1)) / 1e3
+    achieved = algo / avg_s / 1e9
+    traffic = measured_traffic(algo)
+    lat_ms = np.array(lat) * 1e3
+    out = {
+        "metric": "smoothed time steps/s incl. covariances, FP64 vs FP32 form; p50/p99 latency",
+        "value": (p.k + 1) * args.steps / el,
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (seeded generator; per-step Haar-based F, Gaussian G, dense SPD K and C)",
+        "config": {"workload": "one trajectory, n=6, m=3, k=100000, per-step F, dense K and C, "
+                               "states and covariances", "problems": 1, "k": p.k, "n": p.n, "m": p.m},
+        "p50_ms": float(np.percentile(lat_ms, 50)),
+        "p99_ms": float(np.percentile(lat_ms, 99)),
+        "nc_value": (p.k + 1) * nc_steps / nc_el,
+        "phase_ms": phases,
+        "err_vs_oracle": err,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_forward<6,3,raw> (level 0)", "algo_bytes_per_launch": algo,
+                     "avg_launch_ms": avg_s * 1e3, "launches_timed": k_cnt},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p)
+    print(json.dumps(out), flush=True)
+    plan.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -138,6 +138,23 @@ typedef struct {
 
 ks_status ks_plan_layout(const ks_plan *plan, ks_layout *out);
 
+/* Kernel timing (instrumentation).  ks_time_kernels(plan, kind) resets the
+ * plan's accumulators and, for kind != KS_TIME_OFF, makes every later
+ * ks_smooth / ks_smooth_cov / ks_covariances on the plan bracket the selected
+ * launches with a pair of hipEvents recorded on the plan's stream.  After each
+ * call the elapsed time is added up; ks_kernel_time reports the total in
+ * milliseconds and the number of bracketed launches (or sequences). */
+typedef enum {
+    KS_TIME_OFF = 0,
+    KS_TIME_FWD_LEVEL0 = 1,   /* the level-0 forward launch (load, whiten, eliminate) */
+    KS_TIME_BWD_LEVEL0 = 2,   /* the level-0 backward launch                          */
+    KS_TIME_FWD_ALL = 3,      /* all forward launches of a call, as one interval     */
+    KS_TIME_BWD_ALL = 4       /* all backward launches of a call, as one interval    */
+} ks_time_kind;
+
+ks_status ks_time_kernels(ks_plan *plan, int32_t kind);
+ks_status ks_kernel_time(const ks_plan *plan, double *total_ms, int64_t *count);
+
 #ifdef __cplusplus
 }
 #endif

@@ -98,11 +98,35 @@ struct ks_plan {
     Layout lo;
     bool smoothed;
     unsigned host_flags;   // status word copied back after each call
+    // instrumentation (ks_time_kernels)
+    int time_kind;
+    bool time_armed;       // events of the current call were recorded
+    hipEvent_t ev[2];
+    bool ev_made;
+    double time_ms;
+    int64_t time_count;
 };
 
 namespace {
 
 ks_status hip_err(hipError_t e) { return e == hipSuccess ? KS_OK : KS_E_HIP; }
+
+void mark(ks_plan *p, int kind, int which) {
+    if (p->time_kind != kind || !p->ev_made) return;
+    (void)hipEventRecord(p->ev[which], p->stream);
+    if (which == 1) p->time_armed = true;
+}
+
+// add the elapsed time of the bracketed launches (after the stream sync)
+void collect_time(ks_plan *p) {
+    if (!p->time_armed) return;
+    p->time_armed = false;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p->ev[0], p->ev[1]) == hipSuccess) {
+        p->time_ms += ms;
+        p->time_count += 1;
+    }
+}
 
 double *seg_d(ks_plan *p, size_t off) { return reinterpret_cast<double *>(p->ws + off); }
 
@@ -116,6 +140,7 @@ void enqueue_forward(ks_plan *p, const double *H, const double *F, const double 
     double *slots = seg_d(p, lo.off_slots);
     unsigned *flags = reinterpret_cast<unsigned *>(p->ws + lo.off_flags);
     ks::launch_clear_flags(flags, p->stream);
+    mark(p, KS_TIME_FWD_ALL, 0);
     for (int l = 0; l <= lo.L; ++l) {
         ks::FwdArgs a{};
         a.k = p->d.k;
@@ -131,11 +156,14 @@ void enqueue_forward(ks_plan *p, const double *H, const double *F, const double 
         a.rrows = rrows + lo.rec_off[l] * rrec;
         a.slots = slots + 2 * lo.slot_off[l];
         a.flags = flags;
+        if (l == 0) mark(p, KS_TIME_FWD_LEVEL0, 0);
         if (lo.Nl[l] == 1)
             (l == 0 ? p->kset->base_raw : p->kset->base)(a, p->stream);
         else
             (l == 0 ? p->kset->fwd_raw : p->kset->fwd)(a, p->stream);
+        if (l == 0) mark(p, KS_TIME_FWD_LEVEL0, 1);
     }
+    mark(p, KS_TIME_FWD_ALL, 1);
     ks::launch_status(slots, lo.nslots, flags, p->stream);
 }
 
@@ -150,17 +178,21 @@ void enqueue_backward(ks_plan *p, double *u_out, double *cov_out) {
     b.spm = seg_d(p, lo.off_spm);
     b.spm_first = lo.spm_first;
     for (int l = 0; l <= lo.L; ++l) b.rec_off[l] = lo.rec_off[l];
+    mark(p, KS_TIME_BWD_ALL, 0);
     for (int l = lo.L; l >= 0; --l) {
         b.level = l;
         b.units = (lo.Nl[l] + 1) / 2;
         b.store_s = cov_out && l >= 1;
+        if (l == 0) mark(p, KS_TIME_BWD_LEVEL0, 0);
         if (u_out && cov_out)
             p->kset->bwd_both(b, p->stream);
         else if (u_out)
             p->kset->bwd_y(b, p->stream);
         else
             p->kset->bwd_cov(b, p->stream);
+        if (l == 0) mark(p, KS_TIME_BWD_LEVEL0, 1);
     }
+    mark(p, KS_TIME_BWD_ALL, 1);
 }
 
 ks_status finish(ks_plan *p) {
@@ -171,6 +203,7 @@ ks_status finish(ks_plan *p) {
     if (e != hipSuccess) return KS_E_HIP;
     e = hipStreamSynchronize(p->stream);
     if (e != hipSuccess) return KS_E_HIP;
+    collect_time(p);
     const unsigned f = p->host_flags;
     if (f & ks::FLAG_NOT_SPD) return KS_E_NOT_SPD;
     if (f & ks::FLAG_NONFINITE) return KS_E_NONFINITE;
@@ -220,6 +253,11 @@ ks_status ks_create(const ks_desc *desc, void *workspace, size_t ws_bytes, void 
     p->lo = lo;
     p->smoothed = false;
     p->host_flags = 0;
+    p->time_kind = KS_TIME_OFF;
+    p->time_armed = false;
+    p->ev_made = false;
+    p->time_ms = 0.0;
+    p->time_count = 0;
     *out = p;
     return KS_OK;
 }
@@ -254,11 +292,18 @@ ks_status ks_covariances(ks_plan *p, double *cov_out) {
     enqueue_backward(p, nullptr, cov_out);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return KS_E_HIP;
-    return hip_err(hipStreamSynchronize(p->stream));
+    e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return KS_E_HIP;
+    collect_time(p);
+    return KS_OK;
 }
 
 ks_status ks_destroy(ks_plan *p) {
     if (!p) return KS_E_ARG;
+    if (p->ev_made) {
+        (void)hipEventDestroy(p->ev[0]);
+        (void)hipEventDestroy(p->ev[1]);
+    }
     delete p;
     return KS_OK;
 }
@@ -287,6 +332,30 @@ ks_status ks_plan_layout(const ks_plan *p, ks_layout *out) {
         out->level_rec_offset[l] = p->lo.rec_off[l];
         out->level_columns[l] = p->lo.Nl[l];
     }
+    return KS_OK;
+}
+
+ks_status ks_time_kernels(ks_plan *p, int32_t kind) {
+    if (!p || kind < KS_TIME_OFF || kind > KS_TIME_BWD_ALL) return KS_E_ARG;
+    if (kind != KS_TIME_OFF && !p->ev_made) {
+        if (hipEventCreate(&p->ev[0]) != hipSuccess) return KS_E_HIP;
+        if (hipEventCreate(&p->ev[1]) != hipSuccess) {
+            (void)hipEventDestroy(p->ev[0]);
+            return KS_E_HIP;
+        }
+        p->ev_made = true;
+    }
+    p->time_kind = kind;
+    p->time_armed = false;
+    p->time_ms = 0.0;
+    p->time_count = 0;
+    return KS_OK;
+}
+
+ks_status ks_kernel_time(const ks_plan *p, double *total_ms, int64_t *count) {
+    if (!p || !total_ms || !count) return KS_E_ARG;
+    *total_ms = p->time_ms;
+    *count = p->time_count;
     return KS_OK;
 }
 

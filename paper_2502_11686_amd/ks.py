@@ -23,7 +23,9 @@ KS_FP64 = 0
 KS_COV_DENSE, KS_COV_DIAG = 0, 1
 
 SYMBOLS = ("ks_workspace_bytes", "ks_supported", "ks_create", "ks_smooth", "ks_covariances",
-           "ks_smooth_cov", "ks_destroy", "ks_status_string", "ks_plan_layout")
+           "ks_smooth_cov", "ks_destroy", "ks_status_string", "ks_plan_layout",
+           "ks_time_kernels", "ks_kernel_time")
+KS_TIME_OFF, KS_TIME_FWD_LEVEL0, KS_TIME_BWD_LEVEL0, KS_TIME_FWD_ALL, KS_TIME_BWD_ALL = range(5)
 
 
 class Desc(ctypes.Structure):
@@ -76,6 +78,10 @@ def lib():
     L.ks_status_string.argtypes = [ctypes.c_int]
     L.ks_plan_layout.restype = ctypes.c_int
     L.ks_plan_layout.argtypes = [vp, ctypes.POINTER(Layout)]
+    L.ks_time_kernels.restype = ctypes.c_int
+    L.ks_time_kernels.argtypes = [vp, ctypes.c_int32]
+    L.ks_kernel_time.restype = ctypes.c_int
+    L.ks_kernel_time.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
     _lib = L
     return L
 
@@ -204,6 +210,20 @@ class Plan:
         words = self.workspace[off:off + self.ws_bytes].view(torch.float64)
         start = lay["rrow_offset"]
         return words[start:start + (self.k + 1) * lay["rrow_stride"]].view(self.k + 1, n, 3 * n + 1)
+
+    def time_kernels(self, kind: int):
+        """Bracket the selected launches of later calls with hipEvents (0 = off)."""
+        st = lib().ks_time_kernels(self._h, int(kind))
+        if st != KS_OK:
+            raise KsError(st, "ks_time_kernels")
+
+    def kernel_time(self):
+        """(total milliseconds, number of bracketed launches) since time_kernels."""
+        ms, cnt = ctypes.c_double(), ctypes.c_int64()
+        st = lib().ks_kernel_time(self._h, ctypes.byref(ms), ctypes.byref(cnt))
+        if st != KS_OK:
+            raise KsError(st, "ks_kernel_time")
+        return ms.value, cnt.value
 
     def close(self):
         if getattr(self, "_h", None) is not None:
