@@ -14,7 +14,8 @@ enum : unsigned {
     FLAG_RANK = 4u,
 };
 
-constexpr int kBlock = 256;   // threads per workgroup for every level kernel
+constexpr int kBlock = 256;      // threads per workgroup of the per-level kernels
+constexpr int kTailBlock = 512;  // threads of the single-workgroup forward tail
 constexpr int kMaxLevels = 64;
 
 // Arguments of one forward level (odd-even elimination of the even block
@@ -36,11 +37,25 @@ struct FwdArgs {
     unsigned *flags;
 };
 
-// Arguments of one backward level (back-substitution and/or Algorithm 2).
+// Forward levels l0..L in one workgroup, then the rank test.
+struct FwdTailArgs {
+    FwdArgs a;        // shared fields (k, m, layouts, raw inputs, flags)
+    int32_t l0, L;
+    double *sys;      // reduced-system segment
+    double *rrows;    // R-row record 0
+    const double *slots;  // per-block slots of the launches before the tail
+    int64_t nprev;
+    int64_t sys_off[kMaxLevels];
+    int64_t rec_off[kMaxLevels];
+    int64_t Nl[kMaxLevels];
+};
+
+// Arguments of a backward level (back-substitution and/or Algorithm 2); the
+// tail kernel runs levels `level` down to `l_lo`.
 struct BwdArgs {
     int64_t k;
-    int64_t units;    // R-row records at this level
     int32_t level;
+    int32_t l_lo;
     int32_t store_s;  // write S_{i,I} blocks for lower levels
     const double *rrows_all;  // record 0
     const double *u_in;       // u_out (neighbour states)
@@ -49,26 +64,29 @@ struct BwdArgs {
     double *spm;              // S_{i,i-2^l}, S_{i,i+2^l} of records >= spm_first
     int64_t spm_first;
     int64_t rec_off[kMaxLevels];
+    int64_t Nl[kMaxLevels];
 };
+
+enum BwdMode { BWD_Y = 0, BWD_COV = 1, BWD_BOTH = 2 };
 
 // kernels launched by the runtime for state dimension n, observation class mm
 struct KernelSet {
     int n, mm;
     void (*fwd_raw)(const FwdArgs &, hipStream_t);
     void (*fwd)(const FwdArgs &, hipStream_t);
-    void (*base_raw)(const FwdArgs &, hipStream_t);
-    void (*base)(const FwdArgs &, hipStream_t);
-    void (*bwd_y)(const BwdArgs &, hipStream_t);
-    void (*bwd_cov)(const BwdArgs &, hipStream_t);
-    void (*bwd_both)(const BwdArgs &, hipStream_t);
-    int units_per_block_fwd;
-    int units_per_block_bwd;
+    void (*fwd_tail_raw)(const FwdTailArgs &, hipStream_t);  // tail starting at level 0
+    void (*fwd_tail)(const FwdTailArgs &, hipStream_t);
+    void (*bwd[3])(const BwdArgs &, hipStream_t);             // indexed by BwdMode
+    void (*bwd_tail[3])(const BwdArgs &, hipStream_t);
+    int upb_fwd;          // units per workgroup, per-level forward kernel
+    int upb_fwd_tail;     // units per pass of the forward tail
+    int upb_bwd[3];
+    int upb_bwd_tail[3];
 };
 
 // nullptr when (n, m) has no instantiation
 const KernelSet *find_kernels(int n, int m);
 
 void launch_clear_flags(unsigned *flags, hipStream_t s);
-void launch_status(const double *slots, int64_t nslots, unsigned *flags, hipStream_t s);
 
 }  // namespace ks

@@ -9,15 +9,16 @@
 // neighbour j+1 and performs, in registers,
 //   step 1: QR of [O_j ; E-_{j+1}] applied to [0 ; E+_{j+1}] and the rhs
 //           (the paper's QR of [C_i ; -B_{i+1}] producing R~_j, fill X_j, D~_{j+1})
-//   step 3: QR of [D~_{j+1} ; O_{j+1}] -> observation block of reduced column t
+//   step 3: QR of [O_{j+1} ; D~_{j+1}] -> observation block of reduced column t
 //   step 2: QR of [E+_j ; R~_j] applied to [E-_j, 0 ; 0, X_j] and the rhs
 //           (the paper's QR of [D_i ; R~_i]) -> the permanent block row of R
 //           (R_jj, R_j,j+1, rho_j, R_j,j-1) and the reduced evolution block
 //           (Z_j, X~_j | zeta_j) of reduced column t.
-// When N_l is odd the last (even) column has no right neighbour: the last unit
-// also eliminates it, and its Z rows, which touch only column N_l - 2, are
-// stacked into that unit's step-3 QR.  A level with one column is the base
-// case: QR of its observation block.
+// Steps 2 and 3 are independent once step 1 is done.  When N_l is odd the last
+// (even) column has no right neighbour: the last unit also eliminates it, and
+// its Z rows, which touch only column N_l - 2, are stacked into that unit's
+// step-3 QR.  A level with one column is the base case: QR of its observation
+// block.
 //
 // Backward: one launch per level, L down to 0.  For each block row of level l
 // (original column i, neighbours a = i - 2^l and b = i + 2^l) the kernel forms
@@ -25,8 +26,9 @@
 // (Section III-A) and, for Algorithm 2, S_iI = -T S_II and
 // S_ii = R_ii^{-1} R_ii^{-T} - S_iI T^T (returned symmetrized).
 //
-// Mapping to CDNA4: a unit is a group of G lanes (G = 16/32/64 >= 3n+1) inside
-// one 64-wide wavefront.  Lane g of the group owns one column of every stack:
+// Mapping to CDNA4: a unit is a group of G = 3n+1 consecutive lanes of one
+// 64-wide wavefront (floor(64/G) units per wavefront).  Lane g of the group
+// owns one column of every stack:
 //   g in [0, n)      columns of u_j        ("cur")
 //   g in [n, 2n)     columns of u_{j+1}    ("right")
 //   g == 2n          the right-hand side   ("rhs")
@@ -47,20 +49,38 @@ enum Role { CUR = 0, RIGHT = 1, RHS = 2, LEFT = 3, IDLE = 4 };
 
 template <int N>
 struct Geo {
-    static constexpr int COLS = 3 * N + 1;
-    static constexpr int G = COLS <= 16 ? 16 : (COLS <= 32 ? 32 : 64);
-    static constexpr int UPB = kBlock / G;          // units per workgroup
+    static constexpr int G = 3 * N + 1;             // lanes per unit
+    static constexpr int UPW = 64 / G;              // units per wavefront
+    static constexpr int UPB = (kBlock / 64) * UPW; // units per workgroup
     static constexpr int RREC = N * (3 * N + 1);    // R-row record
     static constexpr int OREC = N * (N + 1);        // observation block [O | w]
     static constexpr int EREC = N * (2 * N + 1);    // evolution block [E- | E+ | eta]
     static constexpr int SREC = OREC + EREC;        // reduced-system column
-    static_assert(COLS <= 64, "state dimension too large for the wavefront family");
+    static_assert(G <= 64, "state dimension too large for the wavefront family");
+};
+
+// position of this thread: its unit within the workgroup and its lane in the unit
+template <int N>
+struct Grp {
+    int gl;     // lane within the unit (G for lanes outside any unit)
+    int gbase;  // wavefront lane of the unit's lane 0
+    int ui;     // unit within the workgroup
+    bool in;    // lane belongs to a unit
+    __device__ Grp() {
+        constexpr int G = Geo<N>::G;
+        const int lane = threadIdx.x & 63;
+        const int g = lane / G;
+        in = g < Geo<N>::UPW;
+        gl = in ? lane - g * G : G;
+        gbase = in ? g * G : 0;
+        ui = (threadIdx.x >> 6) * Geo<N>::UPW + (in ? g : 0);
+    }
 };
 
 template <int N>
 struct LaneRole {
-    int gl, role, rc;
-    __device__ explicit LaneRole(int g) : gl(g) {
+    int role, rc;
+    __device__ explicit LaneRole(int g) {
         if (g < N) { role = CUR; rc = g; }
         else if (g < 2 * N) { role = RIGHT; rc = g - N; }
         else if (g == 2 * N) { role = RHS; rc = 0; }
@@ -69,63 +89,99 @@ struct LaneRole {
     }
 };
 
-template <int G>
-__device__ __forceinline__ double gbcast(double v, int src) {
-    return __shfl(v, src, G);
+// value of v on wavefront lane src (ds_bpermute, two dwords)
+__device__ __forceinline__ double bperm(double v, int src) {
+    const int addr = src << 2;
+    const int lo = __builtin_amdgcn_ds_bpermute(addr, __double2loint(v));
+    const int hi = __builtin_amdgcn_ds_bpermute(addr, __double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+
+// 1/d and 1/sqrt(d) from the hardware estimates refined by two Newton steps
+__device__ __forceinline__ double rcp_nr(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(r, fma(-d, r, 1.0), r);
+    r = fma(r, fma(-d, r, 1.0), r);
+    return r;
+}
+
+__device__ __forceinline__ double rsq_nr(double d) {
+    double r = __builtin_amdgcn_rsq(d);
+    const double h = 0.5 * d;
+    r = r * fma(-h * r, r, 1.5);
+    r = r * fma(-h * r, r, 1.5);
+    return r;
 }
 
 // Householder QR of the first NP columns of a column-distributed stack of H
-// rows.  The pivot column p lives on group lane PL0 + p.  Reflector
+// rows.  Pivot column p lives on unit lane pl0 + p.  Reflector
 // P = I - c x' x'^T with x' = (alpha - beta, x_{p+1}, ..., x_{H-1}),
 // beta = -sign(alpha) ||x_{p:}||, c = 1 / (beta (beta - alpha)); a column whose
-// sub-diagonal part is zero gets the identity.
-template <int G, int H, int NP, int PL0>
-__device__ __forceinline__ void hqr(double (&x)[H], int gl) {
+// sub-diagonal part is zero gets the identity.  Every lane applies the
+// reflector to its own column (the pivot lane too); the pivot diagonal is then
+// set to beta and, at the end, the strictly lower parts of the pivot columns
+// are set to zero.
+template <int H, int NP>
+__device__ __forceinline__ void hqr(double (&x)[H], int gl, int gbase, int pl0) {
     constexpr int P = NP < H ? NP : H;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
+        const int src = gbase + pl0 + p;
         const double alpha = x[p];
-        double xn2 = 0.0;
+        double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-        for (int r = p + 1; r < H; ++r) xn2 = fma(x[r], x[r], xn2);
+        for (int r = p + 1; r < H; r += 2) s0 = fma(x[r], x[r], s0);
+#pragma unroll
+        for (int r = p + 2; r < H; r += 2) s1 = fma(x[r], x[r], s1);
+        const double xn2 = s0 + s1;
+        const double s = fma(alpha, alpha, xn2);
+        const double nrm = sqrt(s);
+        const double beta = -copysign(nrm, alpha);
         const bool nz = xn2 != 0.0;
-        const double beta = -copysign(sqrt(fma(alpha, alpha, xn2)), alpha);
+        const double cc = nz ? rcp_nr(fma(fabs(alpha), nrm, s)) : 0.0;
         const double v0 = alpha - beta;
-        const double cc = nz ? 1.0 / (beta * (beta - alpha)) : 0.0;
-        const double cb = gbcast<G>(cc, PL0 + p);
-        const double v0b = gbcast<G>(v0, PL0 + p);
+        const double dnew = nz ? beta : alpha;
+        const double cb = bperm(cc, src);
+        const double v0b = bperm(v0, src);
         double v[H];
 #pragma unroll
-        for (int r = p + 1; r < H; ++r) v[r] = gbcast<G>(x[r], PL0 + p);
-        double w = v0b * x[p];
+        for (int r = p + 1; r < H; ++r) v[r] = bperm(x[r], src);
+        double w0 = v0b * x[p], w1 = 0.0;
 #pragma unroll
-        for (int r = p + 1; r < H; ++r) w = fma(v[r], x[r], w);
-        w *= cb;
-        const bool piv = gl == PL0 + p;
-        x[p] = piv ? (nz ? beta : alpha) : fma(-w, v0b, x[p]);
+        for (int r = p + 1; r < H; r += 2) w0 = fma(v[r], x[r], w0);
 #pragma unroll
-        for (int r = p + 1; r < H; ++r) x[r] = piv ? 0.0 : fma(-w, v[r], x[r]);
+        for (int r = p + 2; r < H; r += 2) w1 = fma(v[r], x[r], w1);
+        const double w = (w0 + w1) * cb;
+        x[p] = (gl == pl0 + p) ? dnew : fma(-w, v0b, x[p]);
+#pragma unroll
+        for (int r = p + 1; r < H; ++r) x[r] = fma(-w, v[r], x[r]);
     }
+    const unsigned q = (unsigned)(gl - pl0);
+#pragma unroll
+    for (int r = 1; r < H; ++r)
+        if (q < (unsigned)(r < P ? r : P)) x[r] = 0.0;
 }
 
 // Whitening by a dense SPD covariance (Section II-A): rows roff..roff+D-1 of
 // every lane's column are replaced by L^{-1} times themselves, where
-// Cov = L L^T.  Lane q < D holds column q of Cov in cv; the Cholesky
-// factorization runs right-looking over the lanes (each lane keeps its column
-// of the symmetric Schur complement, so L(q,p) = cv_q[p] / L(p,p) is local) and
-// is fused with the forward substitution, one broadcast column per pivot.
-template <int G, int H, int D>
+// Cov = L L^T.  Unit lane cl0 + q (q < D) holds column q of Cov in cv (other
+// lanes hold zeros); the Cholesky factorization runs right-looking over those
+// lanes (each keeps its column of the symmetric Schur complement, so
+// L(q,p) = cv_q[p] / L(p,p) is local) and is fused with the forward
+// substitution, one broadcast column of L per pivot.
+template <int H, int D>
 __device__ __forceinline__ void whiten_dense(double (&x)[H], int roff, double (&cv)[D], int gl,
-                                             bool &bad) {
+                                             int gbase, int cl0, bool &bad) {
 #pragma unroll
     for (int p = 0; p < D; ++p) {
+        const int src = gbase + cl0 + p;
         const double piv = cv[p];
-        if (gl == p && !(piv > 0.0 && isfinite(piv))) bad = true;
-        const double il = 1.0 / sqrt(piv);
-        const double ilb = gbcast<G>(il, p);
+        if (gl == cl0 + p && !(piv > 0.0 && isfinite(piv))) bad = true;
+        const double il = rsq_nr(piv);
+        const double ilb = bperm(il, src);
         double lb[D];
 #pragma unroll
-        for (int r = p + 1; r < D; ++r) lb[r] = gbcast<G>(cv[r] * il, p);
+        for (int r = p + 1; r < D; ++r) lb[r] = bperm(cv[r] * il, src);
         const double f = cv[p] * ilb;
 #pragma unroll
         for (int r = p + 1; r < D; ++r) cv[r] = fma(-lb[r], f, cv[r]);
@@ -136,22 +192,21 @@ __device__ __forceinline__ void whiten_dense(double (&x)[H], int roff, double (&
     }
 }
 
-// Whitening by a diagonal covariance: row r scaled by 1/sqrt(var_r).  Rows
-// r >= dv (padding) are left as they are.
+// Whitening by a diagonal covariance: row r scaled by 1/sqrt(var_r).
 template <int H, int D>
-__device__ __forceinline__ void whiten_diag(double (&x)[H], int roff, const double *var, int dv,
-                                            bool valid, int gl, bool &bad) {
+__device__ __forceinline__ void whiten_diag(double (&x)[H], int roff, const double (&var)[D],
+                                            int gl, bool &bad) {
 #pragma unroll
     for (int r = 0; r < D; ++r) {
-        const double v = (valid && r < dv) ? var[r] : 1.0;
+        const double v = var[r];
         if (gl == 0 && !(v > 0.0 && isfinite(v))) bad = true;
-        x[roff + r] *= 1.0 / sqrt(v);
+        x[roff + r] *= rsq_nr(v);
     }
 }
 
 // ---------------------------------------------------------------- loaders
 
-// observation block of a reduced system column: rows [O | w]
+// observation block of a reduced-system column, rows [O | w], onto owner lanes
 template <int N, int H>
 __device__ __forceinline__ void load_obs_sys(double (&x)[H], int roff, const double *obs,
                                              const LaneRole<N> &L, int own, bool valid) {
@@ -161,7 +216,7 @@ __device__ __forceinline__ void load_obs_sys(double (&x)[H], int roff, const dou
     for (int r = 0; r < N; ++r) x[roff + r] = ld ? obs[r * (N + 1) + col] : 0.0;
 }
 
-// evolution block of a reduced system column: rows [E- | E+ | eta]
+// evolution block of a reduced-system column, rows [E- | E+ | eta]
 template <int N, int H>
 __device__ __forceinline__ void load_evol_sys(double (&x)[H], int roff, const double *ev,
                                               const LaneRole<N> &L, int role_m, int role_p,
@@ -174,11 +229,13 @@ __device__ __forceinline__ void load_evol_sys(double (&x)[H], int roff, const do
     for (int r = 0; r < N; ++r) x[roff + r] = ld ? ev[r * (2 * N + 1) + col] : 0.0;
 }
 
-// raw observation step j: W_j [G_j | o_j], m rows padded with zero rows to MM
-template <int N, int MM, int G, int H>
-__device__ __forceinline__ void load_obs_raw(double (&x)[H], int roff, int64_t j,
-                                             const LaneRole<N> &L, int own, const FwdArgs &a,
-                                             bool valid, bool &bad) {
+// Raw observation step j, rows [G_j | o_j] (m rows, zero rows up to MM), and
+// the covariance data for its whitening: cv = column (gl - cl0) of C_j on the
+// lanes cl0 .. cl0+MM-1 (identity columns for padding rows), or the variances.
+template <int N, int MM, int H>
+__device__ __forceinline__ void load_obs_raw(double (&x)[H], int roff, double (&cv)[MM],
+                                             int64_t j, const LaneRole<N> &L, int gl, int own,
+                                             int cl0, const FwdArgs &a, bool valid) {
     const int m = a.m;
     const int col = (L.role == own) ? L.rc : (L.role == RHS ? N : -1);
     const bool ld = valid && col >= 0;
@@ -188,22 +245,25 @@ __device__ __forceinline__ void load_obs_raw(double (&x)[H], int roff, int64_t j
     for (int r = 0; r < MM; ++r)
         x[roff + r] = (ld && r < m) ? (col < N ? Gj[r * N + col] : oj[r]) : 0.0;
     if (a.C_diag) {
-        whiten_diag<H, MM>(x, roff, a.C + j * (int64_t)m, m, valid, L.gl, bad);
+        const double *Cj = a.C + j * (int64_t)m;
+#pragma unroll
+        for (int r = 0; r < MM; ++r) cv[r] = (valid && r < m) ? Cj[r] : 1.0;
     } else {
         const double *Cj = a.C + j * (int64_t)m * m;
-        double cv[MM];
+        const int q = gl - cl0;
+        const bool mine = (unsigned)q < (unsigned)MM;
 #pragma unroll
         for (int r = 0; r < MM; ++r)
-            cv[r] = (valid && L.gl < m && r < m) ? Cj[r * m + L.gl] : (r == L.gl ? 1.0 : 0.0);
-        whiten_dense<G, H, MM>(x, roff, cv, L.gl, bad);
+            cv[r] = !mine ? 0.0 : (valid && q < m && r < m) ? Cj[r * m + q] : (r == q ? 1.0 : 0.0);
     }
 }
 
-// raw evolution step i (1..k): V_i [-F_i | H_i | c_i]; zero block when !valid
-template <int N, int G, int H>
-__device__ __forceinline__ void load_evol_raw(double (&x)[H], int roff, int64_t i,
-                                              const LaneRole<N> &L, int role_m, int role_p,
-                                              const FwdArgs &a, bool valid, bool &bad) {
+// Raw evolution step i (1..k), rows [-F_i | H_i | c_i] (zero block when
+// !valid), with its covariance data as in load_obs_raw.
+template <int N, int H>
+__device__ __forceinline__ void load_evol_raw(double (&x)[H], int roff, double (&cv)[N], int64_t i,
+                                              const LaneRole<N> &L, int gl, int role_m,
+                                              int role_p, int cl0, const FwdArgs &a, bool valid) {
     const int64_t t = i - 1;  // ABI entry of step i
     const double *F = a.F + t * N * N;
     const double *Hm = a.H ? a.H + t * N * N : nullptr;
@@ -219,15 +279,26 @@ __device__ __forceinline__ void load_evol_raw(double (&x)[H], int roff, int64_t 
         x[roff + r] = v;
     }
     if (a.K_diag) {
-        whiten_diag<H, N>(x, roff, a.K + t * N, N, valid, L.gl, bad);
+        const double *Kt = a.K + t * N;
+#pragma unroll
+        for (int r = 0; r < N; ++r) cv[r] = valid ? Kt[r] : 1.0;
     } else {
         const double *Kt = a.K + t * N * N;
-        double cv[N];
+        const int q = gl - cl0;
+        const bool mine = (unsigned)q < (unsigned)N;
 #pragma unroll
         for (int r = 0; r < N; ++r)
-            cv[r] = (valid && L.gl < N) ? Kt[r * N + L.gl] : (r == L.gl ? 1.0 : 0.0);
-        whiten_dense<G, H, N>(x, roff, cv, L.gl, bad);
+            cv[r] = !mine ? 0.0 : valid ? Kt[r * N + q] : (r == q ? 1.0 : 0.0);
     }
+}
+
+template <int H, int D>
+__device__ __forceinline__ void whiten(bool diag, double (&x)[H], int roff, double (&cv)[D],
+                                       int gl, int gbase, int cl0, bool &bad) {
+    if (diag)
+        whiten_diag<H, D>(x, roff, cv, gl, bad);
+    else
+        whiten_dense<H, D>(x, roff, cv, gl, gbase, cl0, bad);
 }
 
 // ------------------------------------------------------ shared epilogues
@@ -245,11 +316,11 @@ __device__ __forceinline__ void diag_stats(const double (&x)[H], const LaneRole<
     dmax = fmax(dmax, d);
 }
 
-// block-wide min/max of |R_pp| into slots[2*blockIdx], error bits into flags
-__device__ __forceinline__ void block_epilogue(double dmin, double dmax, bool bad,
-                                               bool nonfinite, double *slots,
-                                               unsigned *flags) {
-    __shared__ double red[2][kBlock / 64];
+// workgroup min/max of |R_pp| (result valid in thread 0), error bits into flags
+template <int TB>
+__device__ __forceinline__ void block_minmax(double &dmin, double &dmax, bool bad, bool nonfinite,
+                                             unsigned *flags) {
+    __shared__ double red[2][TB / 64];
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
         dmin = fmin(dmin, __shfl_xor(dmin, off));
@@ -264,13 +335,13 @@ __device__ __forceinline__ void block_epilogue(double dmin, double dmax, bool ba
     if (nonfinite) atomicOr(flags, FLAG_NONFINITE);
     __syncthreads();
     if (threadIdx.x == 0) {
-        double a = red[0][0], b = red[1][0];
-        for (int w = 1; w < kBlock / 64; ++w) {
-            a = fmin(a, red[0][w]);
-            b = fmax(b, red[1][w]);
+#pragma unroll
+        for (int w = 1; w < TB / 64; ++w) {
+            red[0][0] = fmin(red[0][0], red[0][w]);
+            red[1][0] = fmax(red[1][0], red[1][w]);
         }
-        slots[2 * blockIdx.x] = a;
-        slots[2 * blockIdx.x + 1] = b;
+        dmin = red[0][0];
+        dmax = red[1][0];
     }
 }
 
@@ -284,60 +355,57 @@ __device__ __forceinline__ void store_rrow(double *rec, const double (&x)[H], in
 
 // ------------------------------------------------------------- forward level
 
+// One unit of a forward level: even column j = 2t and its right neighbour
+// (plus the last column when it is the folding unit).  No workgroup barrier.
 template <int N, int MM, bool RAW>
-__global__ __launch_bounds__(kBlock) void k_forward(FwdArgs a) {
+__device__ __forceinline__ void fwd_unit(const FwdArgs &a, int64_t t, bool in, int gl, int gb,
+                                         double &dmin, double &dmax, bool &bad, bool &nonfinite) {
     using GE = Geo<N>;
-    constexpr int G = GE::G;
-    constexpr int RO = RAW ? MM : N;           // rows of an observation block
+    constexpr int RO = RAW ? MM : N;            // rows of an observation block
     constexpr int HA = RO + N, HB = 2 * RO, HC = 2 * N;
-    constexpr int PB = HB < N ? HB : N;        // rows of the step-3 triangle
-    const int gl = threadIdx.x % G;
-    const int64_t t = (int64_t)blockIdx.x * GE::UPB + threadIdx.x / G;
-    const bool valid = t < a.units;
+    constexpr int PB = HB < N ? HB : N;         // rows of the step-3 triangle
+    const bool valid = in && t < a.units;
     const LaneRole<N> L(gl);
     const int64_t j = 2 * t;
     const bool fold = valid && (a.Nl & 1) && t == a.units - 1;
-    bool bad = false, nonfinite = false;
-    double dmin = INFINITY, dmax = 0.0;
 
-    // step 1: [O_j | 0 | w_j ; E-_{j+1} | E+_{j+1} | eta_{j+1}], pivots on cur lanes
-    double A[HA];
+    // A = [O_j | 0 | w_j ; E-_{j+1} | E+_{j+1} | eta_{j+1}]      (cur, right, rhs lanes)
+    // B = [D~_{j+1} | gamma ; O_{j+1} | w_{j+1}]                  (right, rhs lanes)
+    // C = [E+_j | 0 | eta_j | E-_j ; R~_j | X_j | rho~_j | 0]     (cur, right, rhs, left lanes)
+    double A[HA], B[HB], C[HC];
+#pragma unroll
+    for (int r = N; r < HC; ++r) C[r] = 0.0;
     if constexpr (RAW) {
-        load_obs_raw<N, MM, G>(A, 0, j, L, CUR, a, valid, bad);
-        load_evol_raw<N, G>(A, RO, j + 1, L, CUR, RIGHT, a, valid, bad);
+        double cvOa[MM], cvOb[MM], cvEa[N], cvEc[N];
+        load_obs_raw<N, MM>(A, 0, cvOa, j, L, gl, CUR, 0, a, valid);
+        load_evol_raw<N>(A, RO, cvEa, j + 1, L, gl, CUR, RIGHT, 0, a, valid);
+        load_obs_raw<N, MM>(B, RO, cvOb, j + 1, L, gl, RIGHT, N, a, valid);
+        load_evol_raw<N>(C, 0, cvEc, j, L, gl, LEFT, CUR, 2 * N + 1, a, valid && j >= 1);
+        whiten<HA, MM>(a.C_diag, A, 0, cvOa, gl, gb, 0, bad);
+        whiten<HA, N>(a.K_diag, A, RO, cvEa, gl, gb, 0, bad);
+        whiten<HB, MM>(a.C_diag, B, RO, cvOb, gl, gb, N, bad);
+        whiten<HC, N>(a.K_diag, C, 0, cvEc, gl, gb, 2 * N + 1, bad);
     } else {
         const double *rec = a.sys_in + j * GE::SREC;
         load_obs_sys<N>(A, 0, rec, L, CUR, valid);
         load_evol_sys<N>(A, RO, rec + GE::SREC + GE::OREC, L, CUR, RIGHT, valid);
+        load_obs_sys<N>(B, RO, rec + GE::SREC, L, RIGHT, valid);
+        load_evol_sys<N>(C, 0, rec + GE::OREC, L, LEFT, CUR, valid && j >= 1);
     }
-    hqr<G, HA, N, 0>(A, gl);
 
-    // step 3: [D~_{j+1} | gamma ; O_{j+1} | w_{j+1}], pivots on right lanes
-    double B[HB];
+    // step 1 (pivots on cur lanes)
+    hqr<HA, N>(A, gl, gb, 0);
 #pragma unroll
     for (int r = 0; r < RO; ++r) B[r] = A[N + r];
-    if constexpr (RAW) {
-        load_obs_raw<N, MM, G>(B, RO, j + 1, L, RIGHT, a, valid, bad);
-    } else {
-        load_obs_sys<N>(B, RO, a.sys_in + (j + 1) * GE::SREC, L, RIGHT, valid);
-    }
-    hqr<G, HB, N, N>(B, gl);
-    double Onew[N];
 #pragma unroll
-    for (int r = 0; r < N; ++r) Onew[r] = r < PB ? B[r] : 0.0;
+    for (int r = 0; r < N; ++r) C[N + r] = A[r];
 
-    // step 2: [E+_j | 0 | eta_j | E-_j ; R~_j | X_j | rho~_j | 0], pivots on cur lanes
-    double Cs[HC];
-    if constexpr (RAW) {
-        load_evol_raw<N, G>(Cs, 0, j, L, LEFT, CUR, a, valid && j >= 1, bad);
-    } else {
-        load_evol_sys<N>(Cs, 0, a.sys_in + j * GE::SREC + GE::OREC, L, LEFT, CUR, valid && j >= 1);
-    }
-#pragma unroll
-    for (int r = 0; r < N; ++r) Cs[N + r] = A[r];
-    hqr<G, HC, N, 0>(Cs, gl);
-    store_rrow<N>(a.rrows + t * GE::RREC, Cs, gl, valid);
-    diag_stats<N>(Cs, L, valid, dmin, dmax, nonfinite);
+    // step 3 (pivots on right lanes) and step 2 (pivots on cur lanes)
+    hqr<HB, N>(B, gl, gb, N);
+    hqr<HC, N>(C, gl, gb, 0);
+
+    store_rrow<N>(a.rrows + t * GE::RREC, C, gl, valid);
+    diag_stats<N>(C, L, valid, dmin, dmax, nonfinite);
     // reduced column t, evolution block (Z_j | X~_j | zeta_j) from the bottom of step 2
     if (valid) {
         const int ec = L.role == LEFT ? L.rc
@@ -346,41 +414,45 @@ __global__ __launch_bounds__(kBlock) void k_forward(FwdArgs a) {
         if (ec >= 0) {
             double *rec = a.sys_out + t * GE::SREC + GE::OREC;
 #pragma unroll
-            for (int r = 0; r < N; ++r) rec[r * (2 * N + 1) + ec] = Cs[N + r];
+            for (int r = 0; r < N; ++r) rec[r * (2 * N + 1) + ec] = C[N + r];
         }
     }
+    double Onew[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) Onew[r] = r < PB ? B[r] : 0.0;
 
     if (fold) {
         // the last column jl = N_l - 1 (even, no right neighbour)
         const int64_t jl = a.Nl - 1;
-        double A2[RO];
+        double A2[RO], C2[HC];
+#pragma unroll
+        for (int r = N; r < HC; ++r) C2[r] = 0.0;
         if constexpr (RAW) {
-            load_obs_raw<N, MM, G>(A2, 0, jl, L, CUR, a, true, bad);
+            double cvO[MM], cvE[N];
+            load_obs_raw<N, MM>(A2, 0, cvO, jl, L, gl, CUR, 0, a, true);
+            load_evol_raw<N>(C2, 0, cvE, jl, L, gl, LEFT, CUR, 2 * N + 1, a, true);
+            whiten<RO, MM>(a.C_diag, A2, 0, cvO, gl, gb, 0, bad);
+            whiten<HC, N>(a.K_diag, C2, 0, cvE, gl, gb, 2 * N + 1, bad);
         } else {
             load_obs_sys<N>(A2, 0, a.sys_in + jl * GE::SREC, L, CUR, true);
-        }
-        hqr<G, RO, N, 0>(A2, gl);
-        double C2[HC];
-        if constexpr (RAW) {
-            load_evol_raw<N, G>(C2, 0, jl, L, LEFT, CUR, a, true, bad);
-        } else {
             load_evol_sys<N>(C2, 0, a.sys_in + jl * GE::SREC + GE::OREC, L, LEFT, CUR, true);
         }
+        hqr<RO, N>(A2, gl, gb, 0);
 #pragma unroll
         for (int r = 0; r < N; ++r) C2[N + r] = r < RO ? A2[r] : 0.0;
-        hqr<G, HC, N, 0>(C2, gl);
+        hqr<HC, N>(C2, gl, gb, 0);
         store_rrow<N>(a.rrows + (t + 1) * GE::RREC, C2, gl, true);
         diag_stats<N>(C2, L, true, dmin, dmax, nonfinite);
         // Z rows (left lanes) move onto the right lanes; rhs keeps zeta
-        const int src = (L.role == RIGHT) ? gl + N + 1 : gl;
+        const int src = gb + ((L.role == RIGHT) ? gl + N + 1 : gl);
         double B2[2 * N];
 #pragma unroll
         for (int r = 0; r < N; ++r) {
-            const double z = __shfl(C2[N + r], src, G);
+            const double z = bperm(C2[N + r], src);
             B2[r] = Onew[r];
             B2[N + r] = (L.role == RIGHT || L.role == RHS) ? z : 0.0;
         }
-        hqr<G, 2 * N, N, N>(B2, gl);
+        hqr<2 * N, N>(B2, gl, gb, N);
 #pragma unroll
         for (int r = 0; r < N; ++r) Onew[r] = B2[r];
     }
@@ -394,34 +466,109 @@ __global__ __launch_bounds__(kBlock) void k_forward(FwdArgs a) {
             for (int r = 0; r < N; ++r) rec[r * (N + 1) + oc] = Onew[r];
         }
     }
-    block_epilogue(dmin, dmax, bad, nonfinite, a.slots, a.flags);
 }
 
-// base case: a level with a single column; R = triangular factor of its
-// observation block (Section III, recursion end; Algorithm 2, one column)
+// Base case: a level with a single column; R = triangular factor of its
+// observation block (Section III, recursion end; Algorithm 2, one column).
 template <int N, int MM, bool RAW>
-__global__ __launch_bounds__(kBlock) void k_base(FwdArgs a) {
-    using GE = Geo<N>;
-    constexpr int G = GE::G;
+__device__ __forceinline__ void base_unit(const FwdArgs &a, bool valid, int gl, int gb,
+                                          double &dmin, double &dmax, bool &bad, bool &nonfinite) {
     constexpr int RO = RAW ? MM : N;
-    const int gl = threadIdx.x % G;
-    const bool valid = threadIdx.x < G;
     const LaneRole<N> L(gl);
-    bool bad = false, nonfinite = false;
-    double dmin = INFINITY, dmax = 0.0;
     double A[RO];
     if constexpr (RAW) {
-        load_obs_raw<N, MM, G>(A, 0, 0, L, CUR, a, valid, bad);
+        double cv[MM];
+        load_obs_raw<N, MM>(A, 0, cv, 0, L, gl, CUR, 0, a, valid);
+        whiten<RO, MM>(a.C_diag, A, 0, cv, gl, gb, 0, bad);
     } else {
         load_obs_sys<N>(A, 0, a.sys_in, L, CUR, valid);
     }
-    hqr<G, RO, N, 0>(A, gl);
+    hqr<RO, N>(A, gl, gb, 0);
     double R[N];
 #pragma unroll
     for (int r = 0; r < N; ++r) R[r] = (r < RO && (L.role == CUR || L.role == RHS)) ? A[r] : 0.0;
     store_rrow<N>(a.rrows, R, gl, valid);
     diag_stats<N>(R, L, valid, dmin, dmax, nonfinite);
-    block_epilogue(dmin, dmax, bad, nonfinite, a.slots, a.flags);
+}
+
+// min/max of the nprev per-block slots of earlier launches into (dmin, dmax),
+// eight independent loads in flight per thread
+__device__ __forceinline__ void reduce_slots(const double *slots, int64_t nprev, double &dmin,
+                                             double &dmax) {
+    for (int64_t s0 = threadIdx.x; s0 < nprev; s0 += 8 * (int64_t)blockDim.x) {
+        double lo[8], hi[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t s = s0 + (int64_t)u * blockDim.x;
+            lo[u] = s < nprev ? slots[2 * s] : INFINITY;
+            hi[u] = s < nprev ? slots[2 * s + 1] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            dmin = fmin(dmin, lo[u]);
+            dmax = fmax(dmax, hi[u]);
+        }
+    }
+}
+
+__device__ __forceinline__ void rank_flag(double dmin, double dmax, unsigned *flags) {
+    if (threadIdx.x == 0 && !(dmin > 64.0 * 2.220446049250313e-16 * dmax))
+        atomicOr(flags, FLAG_RANK);
+}
+
+// one forward level, one unit per G lanes, many workgroups
+template <int N, int MM, bool RAW>
+__global__ __launch_bounds__(kBlock) void k_forward(FwdArgs a) {
+    const Grp<N> g;
+    bool bad = false, nonfinite = false;
+    double dmin = INFINITY, dmax = 0.0;
+    const int64_t t = (int64_t)blockIdx.x * Geo<N>::UPB + g.ui;
+    fwd_unit<N, MM, RAW>(a, t, g.in, g.gl, g.gbase, dmin, dmax, bad, nonfinite);
+    block_minmax<kBlock>(dmin, dmax, bad, nonfinite, a.flags);
+    if (threadIdx.x == 0) {
+        a.slots[2 * blockIdx.x] = dmin;
+        a.slots[2 * blockIdx.x + 1] = dmax;
+    }
+}
+
+// Levels l0..L in one workgroup (the small levels at the top of the
+// recursion): each level is a loop of unit passes, levels are separated by a
+// device-scope fence and a workgroup barrier.  Ends with the rank test over
+// the per-block slots of the earlier launches and its own diagonal.
+template <int N, int MM, bool RAW0>
+__global__ __launch_bounds__(kTailBlock) void k_fwd_tail(FwdTailArgs ta) {
+    using GE = Geo<N>;
+    constexpr int UPB = (kTailBlock / 64) * GE::UPW;
+    const Grp<N> g;
+    bool bad = false, nonfinite = false;
+    double dmin = INFINITY, dmax = 0.0;
+    for (int l = ta.l0; l <= ta.L; ++l) {
+        FwdArgs a = ta.a;
+        a.Nl = ta.Nl[l];
+        a.units = a.Nl == 1 ? 1 : a.Nl / 2;
+        a.level = l;
+        a.sys_in = l >= 1 ? ta.sys + ta.sys_off[l] : nullptr;
+        a.sys_out = l < ta.L ? ta.sys + ta.sys_off[l + 1] : nullptr;
+        a.rrows = ta.rrows + ta.rec_off[l] * GE::RREC;
+        if (a.Nl == 1) {
+            if (RAW0 && l == 0)
+                base_unit<N, MM, true>(a, g.in && g.ui == 0, g.gl, g.gbase, dmin, dmax, bad, nonfinite);
+            else
+                base_unit<N, MM, false>(a, g.in && g.ui == 0, g.gl, g.gbase, dmin, dmax, bad, nonfinite);
+        } else {
+            for (int64_t t0 = 0; t0 < a.units; t0 += UPB) {
+                if (RAW0 && l == 0)
+                    fwd_unit<N, MM, true>(a, t0 + g.ui, g.in, g.gl, g.gbase, dmin, dmax, bad, nonfinite);
+                else
+                    fwd_unit<N, MM, false>(a, t0 + g.ui, g.in, g.gl, g.gbase, dmin, dmax, bad, nonfinite);
+            }
+        }
+        __threadfence();
+        __syncthreads();
+    }
+    reduce_slots(ta.slots, ta.nprev, dmin, dmax);
+    block_minmax<kTailBlock>(dmin, dmax, bad, nonfinite, ta.a.flags);
+    rank_flag(dmin, dmax, ta.a.flags);
 }
 
 // ------------------------------------------------------------ backward level
@@ -443,24 +590,22 @@ struct BwdSmem {
     static constexpr int PER = RR + YI + SI + TT + RI + PP + SS;
 };
 
+// One block row of level l (record t): back-substitution and/or the SelInv
+// step of Algorithm 2.  Uses this unit's LDS region and workgroup barriers, so
+// every thread of the workgroup must call it the same number of times.
 template <int N, bool DO_Y, bool DO_COV>
-__global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a) {
+__device__ __forceinline__ void bwd_unit(const BwdArgs &a, int l, int64_t t, int64_t units,
+                                         bool store_s, bool in, int gl, double *Rr) {
     using GE = Geo<N>;
     using SM = BwdSmem<N, DO_Y, DO_COV>;
     constexpr int G = GE::G;
     constexpr int W = 3 * N + 1;      // R-row width
     constexpr int TW = 2 * N + 1;     // T columns: [T+ | z | T-]
-    __shared__ double smem[GE::UPB * SM::PER];
-    const int gl = threadIdx.x % G;
-    const int ui = threadIdx.x / G;
-    const int64_t t = (int64_t)blockIdx.x * GE::UPB + ui;
-    const bool valid = t < a.units;
-    const int l = a.level;
+    const bool valid = in && t < units;
     const int64_t i = ((2 * t + 1) << l) - 1;
     const int64_t aa = i - ((int64_t)1 << l), bb = i + ((int64_t)1 << l);
     const bool va = valid && aa >= 0, vb = valid && bb <= a.k;
 
-    double *Rr = smem + ui * SM::PER;
     double *yI = Rr + SM::RR;
     double *SII = yI + SM::YI;
     double *TT = SII + SM::SI;
@@ -468,41 +613,43 @@ __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a) {
     double *PP = RI + SM::RI;
     double *SS = PP + SM::PP;
 
-    // stage the record and the neighbour data
-    const double *rec = a.rrows_all + (a.rec_off[l] + t) * GE::RREC;
-    for (int e = gl; e < SM::RR; e += G) Rr[e] = valid ? rec[e] : (e % (W + 1) == 0 ? 1.0 : 0.0);
-    if constexpr (DO_Y) {
-        for (int e = gl; e < 2 * N; e += G) {
-            const bool left = e < N;
-            const int64_t src = left ? aa : bb;
-            yI[e] = (left ? va : vb) ? a.u_in[src * N + (left ? e : e - N)] : 0.0;
-        }
-    }
-    if constexpr (DO_COV) {
-        // S_II = [S_aa S_ab ; S_ab^T S_bb] (row-major 2n x 2n)
-        const double *sab = nullptr;
-        bool trans = false;
-        if (va && vb) {
-            const int la = __builtin_ctzll((unsigned long long)(aa + 1));
-            if (la == l + 1) {
-                sab = a.spm + (rec_of(aa, a.rec_off) - a.spm_first) * 2 * N * N + N * N;  // S_a,b
-            } else {
-                sab = a.spm + (rec_of(bb, a.rec_off) - a.spm_first) * 2 * N * N;          // S_b,a
-                trans = true;
+    // stage the record and the neighbour data (lanes outside a unit skip)
+    if (in) {
+        const double *rec = a.rrows_all + (a.rec_off[l] + t) * GE::RREC;
+        for (int e = gl; e < SM::RR; e += G) Rr[e] = valid ? rec[e] : (e % (W + 1) == 0 ? 1.0 : 0.0);
+        if constexpr (DO_Y) {
+            for (int e = gl; e < 2 * N; e += G) {
+                const bool left = e < N;
+                const int64_t src = left ? aa : bb;
+                yI[e] = (left ? va : vb) ? a.u_in[src * N + (left ? e : e - N)] : 0.0;
             }
         }
-        for (int e = gl; e < 4 * N * N; e += G) {
-            const int r = e / (2 * N), c = e % (2 * N);
-            double v = 0.0;
-            if (r < N && c < N) {
-                if (va) v = a.cov[aa * N * N + r * N + c];
-            } else if (r >= N && c >= N) {
-                if (vb) v = a.cov[bb * N * N + (r - N) * N + (c - N)];
-            } else if (sab) {
-                const int rr = r < N ? r : c, cc = r < N ? c - N : r - N;  // S_ab(rr, cc)
-                v = trans ? sab[cc * N + rr] : sab[rr * N + cc];
+        if constexpr (DO_COV) {
+            // S_II = [S_aa S_ab ; S_ab^T S_bb] (row-major 2n x 2n)
+            const double *sab = nullptr;
+            bool trans = false;
+            if (va && vb) {
+                const int la = __builtin_ctzll((unsigned long long)(aa + 1));
+                if (la == l + 1) {
+                    sab = a.spm + (rec_of(aa, a.rec_off) - a.spm_first) * 2 * N * N + N * N;  // S_a,b
+                } else {
+                    sab = a.spm + (rec_of(bb, a.rec_off) - a.spm_first) * 2 * N * N;          // S_b,a
+                    trans = true;
+                }
             }
-            SII[e] = v;
+            for (int e = gl; e < 4 * N * N; e += G) {
+                const int r = e / (2 * N), c = e % (2 * N);
+                double v = 0.0;
+                if (r < N && c < N) {
+                    if (va) v = a.cov[aa * N * N + r * N + c];
+                } else if (r >= N && c >= N) {
+                    if (vb) v = a.cov[bb * N * N + (r - N) * N + (c - N)];
+                } else if (sab) {
+                    const int rr = r < N ? r : c, cc = r < N ? c - N : r - N;  // S_ab(rr, cc)
+                    v = trans ? sab[cc * N + rr] : sab[rr * N + cc];
+                }
+                SII[e] = v;
+            }
         }
     }
     __syncthreads();
@@ -510,15 +657,18 @@ __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a) {
     // triangular solves with R_ii: lanes < n -> columns of R_ii^{-1},
     // lanes n..3n -> T+ columns, z = R_ii^{-1} rho, T- columns
     if (gl < W && (DO_COV || gl >= N)) {
-        double x[N];
+        double x[N], dinv[N];
 #pragma unroll
-        for (int r = 0; r < N; ++r) x[r] = gl < N ? (r == gl ? 1.0 : 0.0) : Rr[r * W + gl];
+        for (int r = 0; r < N; ++r) {
+            x[r] = gl < N ? (r == gl ? 1.0 : 0.0) : Rr[r * W + gl];
+            dinv[r] = rcp_nr(Rr[r * W + r]);
+        }
 #pragma unroll
         for (int r = N - 1; r >= 0; --r) {
             double acc = x[r];
 #pragma unroll
             for (int s = r + 1; s < N; ++s) acc = fma(-Rr[r * W + s], x[s], acc);
-            x[r] = acc / Rr[r * W + r];
+            x[r] = acc * dinv[r];
         }
         if (gl < N) {
 #pragma unroll
@@ -537,10 +687,12 @@ __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a) {
 
     if constexpr (DO_Y) {
         if (valid && gl < N) {
-            double y = TT[gl * TW + N];
+            double y0 = TT[gl * TW + N], y1 = 0.0;
 #pragma unroll
-            for (int d = 0; d < 2 * N; ++d) y = fma(-TI(gl, d), yI[d], y);
-            a.u_out[i * N + gl] = y;
+            for (int d = 0; d < 2 * N; d += 2) y0 = fma(-TI(gl, d), yI[d], y0);
+#pragma unroll
+            for (int d = 1; d < 2 * N; d += 2) y1 = fma(-TI(gl, d), yI[d], y1);
+            a.u_out[i * N + gl] = y0 + y1;
         }
     }
 
@@ -558,7 +710,7 @@ __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a) {
             }
 #pragma unroll
             for (int r = 0; r < N; ++r) PP[r * 2 * N + gl] = p[r];
-            if (valid && a.store_s) {
+            if (valid && store_s) {
                 const int64_t ri = a.rec_off[l] + t - a.spm_first;
                 double *dst = a.spm + ri * 2 * N * N + (gl < N ? 0 : N * N);
                 const int c = gl < N ? gl : gl - N;
@@ -594,6 +746,35 @@ __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a) {
                 a.cov[i * N * N + r * N + gl] = 0.5 * (SS[r * N + gl] + SS[gl * N + r]);
         }
     }
+    __syncthreads();  // the LDS region is reused by the next call
+}
+
+template <int N, bool DO_Y, bool DO_COV>
+__global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a) {
+    using SM = BwdSmem<N, DO_Y, DO_COV>;
+    __shared__ double smem[Geo<N>::UPB * SM::PER];
+    const Grp<N> g;
+    const int l = a.level;
+    const int64_t t = (int64_t)blockIdx.x * Geo<N>::UPB + g.ui;
+    bwd_unit<N, DO_Y, DO_COV>(a, l, t, (a.Nl[l] + 1) / 2, a.store_s && l >= 1, g.in, g.gl,
+                              smem + g.ui * SM::PER);
+}
+
+// levels a.level down to a.l_lo in one workgroup of TB threads
+template <int N, bool DO_Y, bool DO_COV, int TB>
+__global__ __launch_bounds__(TB) void k_bwd_tail(BwdArgs a) {
+    using SM = BwdSmem<N, DO_Y, DO_COV>;
+    constexpr int UPB = (TB / 64) * Geo<N>::UPW;
+    __shared__ double smem[UPB * SM::PER];
+    const Grp<N> g;
+    for (int l = a.level; l >= a.l_lo; --l) {
+        const int64_t units = (a.Nl[l] + 1) / 2;
+        for (int64_t t0 = 0; t0 < units; t0 += UPB)
+            bwd_unit<N, DO_Y, DO_COV>(a, l, t0 + g.ui, units, a.store_s && l >= 1, g.in, g.gl,
+                                      smem + g.ui * SM::PER);
+        __threadfence();
+        __syncthreads();
+    }
 }
 
 // ----------------------------------------------------------------- status
@@ -602,39 +783,18 @@ __global__ void k_clear_flags(unsigned *flags) {
     if (threadIdx.x == 0) flags[0] = 0u;
 }
 
-__global__ __launch_bounds__(kBlock) void k_status(const double *slots, int64_t nslots,
-                                                   unsigned *flags) {
-    __shared__ double red[2][kBlock];
-    double lo = INFINITY, hi = 0.0;
-    for (int64_t s = threadIdx.x; s < nslots; s += kBlock) {
-        lo = fmin(lo, slots[2 * s]);
-        hi = fmax(hi, slots[2 * s + 1]);
-    }
-    red[0][threadIdx.x] = lo;
-    red[1][threadIdx.x] = hi;
-    __syncthreads();
-    for (int off = kBlock / 2; off >= 1; off >>= 1) {
-        if (threadIdx.x < off) {
-            red[0][threadIdx.x] = fmin(red[0][threadIdx.x], red[0][threadIdx.x + off]);
-            red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + off]);
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        const double dmin = red[0][0], dmax = red[1][0];
-        if (!(dmin > 64.0 * 2.220446049250313e-16 * dmax)) atomicOr(flags, FLAG_RANK);
-    }
-}
-
 void launch_clear_flags(unsigned *flags, hipStream_t s) {
     hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(64), 0, s, flags);
 }
 
-void launch_status(const double *slots, int64_t nslots, unsigned *flags, hipStream_t s) {
-    hipLaunchKernelGGL(k_status, dim3(1), dim3(kBlock), 0, s, slots, nslots, flags);
-}
-
 // -------------------------------------------------------------- dispatch
+
+template <int N, bool Y, bool COV>
+struct BwdTailBlock {
+    // largest of 512 / 256 threads whose LDS stays within 96 KB
+    static constexpr int PER = BwdSmem<N, Y, COV>::PER;
+    static constexpr int TB = (8 * Geo<N>::UPW * PER * 8 <= 96 * 1024) ? 512 : kBlock;
+};
 
 template <int N, int MM, bool RAW>
 static void launch_fwd_t(const FwdArgs &a, hipStream_t s) {
@@ -642,15 +802,22 @@ static void launch_fwd_t(const FwdArgs &a, hipStream_t s) {
     hipLaunchKernelGGL((k_forward<N, MM, RAW>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
 }
 
-template <int N, int MM, bool RAW>
-static void launch_base_t(const FwdArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((k_base<N, MM, RAW>), dim3(1), dim3(kBlock), 0, s, a);
+template <int N, int MM, bool RAW0>
+static void launch_fwd_tail_t(const FwdTailArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL((k_fwd_tail<N, MM, RAW0>), dim3(1), dim3(kTailBlock), 0, s, a);
 }
 
 template <int N, bool Y, bool COV>
 static void launch_bwd_t(const BwdArgs &a, hipStream_t s) {
-    const int64_t blocks = (a.units + Geo<N>::UPB - 1) / Geo<N>::UPB;
+    const int64_t units = (a.Nl[a.level] + 1) / 2;
+    const int64_t blocks = (units + Geo<N>::UPB - 1) / Geo<N>::UPB;
     hipLaunchKernelGGL((k_backward<N, Y, COV>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
+}
+
+template <int N, bool Y, bool COV>
+static void launch_bwd_tail_t(const BwdArgs &a, hipStream_t s) {
+    constexpr int TB = BwdTailBlock<N, Y, COV>::TB;
+    hipLaunchKernelGGL((k_bwd_tail<N, Y, COV, TB>), dim3(1), dim3(TB), 0, s, a);
 }
 
 template <int N, int MM>
@@ -659,19 +826,25 @@ static constexpr KernelSet make_set() {
                      MM,
                      &launch_fwd_t<N, MM, true>,
                      &launch_fwd_t<N, MM, false>,
-                     &launch_base_t<N, MM, true>,
-                     &launch_base_t<N, MM, false>,
-                     &launch_bwd_t<N, true, false>,
-                     &launch_bwd_t<N, false, true>,
-                     &launch_bwd_t<N, true, true>,
+                     &launch_fwd_tail_t<N, MM, true>,
+                     &launch_fwd_tail_t<N, MM, false>,
+                     {&launch_bwd_t<N, true, false>, &launch_bwd_t<N, false, true>,
+                      &launch_bwd_t<N, true, true>},
+                     {&launch_bwd_tail_t<N, true, false>, &launch_bwd_tail_t<N, false, true>,
+                      &launch_bwd_tail_t<N, true, true>},
                      Geo<N>::UPB,
-                     Geo<N>::UPB};
+                     (kTailBlock / 64) * Geo<N>::UPW,
+                     {Geo<N>::UPB, Geo<N>::UPB, Geo<N>::UPB},
+                     {(BwdTailBlock<N, true, false>::TB / 64) * Geo<N>::UPW,
+                      (BwdTailBlock<N, false, true>::TB / 64) * Geo<N>::UPW,
+                      (BwdTailBlock<N, true, true>::TB / 64) * Geo<N>::UPW}};
 }
 
 #define KS_SETS(N) make_set<N, (N + 1) / 2>(), make_set<N, N>(), make_set<N, 2 * N>()
 
 static const KernelSet kSets[] = {
-    KS_SETS(1), KS_SETS(2), KS_SETS(3), KS_SETS(4), KS_SETS(6), KS_SETS(8),
+    make_set<1, 1>(), make_set<1, 2>(), KS_SETS(2), KS_SETS(3), KS_SETS(4), KS_SETS(5),
+    KS_SETS(6),       KS_SETS(8),
 };
 
 const KernelSet *find_kernels(int n, int m) {

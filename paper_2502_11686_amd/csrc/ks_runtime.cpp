@@ -9,6 +9,7 @@
 // by level (ceil(N_l / 2) records at level l).
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -64,7 +65,7 @@ bool make_layout(const ks_desc *d, const ks::KernelSet *ks_, Layout *lo) {
         }
         rec += (N + 1) / 2;
         const int64_t units = N == 1 ? 1 : N / 2;
-        slots += N == 1 ? 1 : (units + ks_->units_per_block_fwd - 1) / ks_->units_per_block_fwd;
+        slots += N == 1 ? 1 : (units + ks_->upb_fwd - 1) / ks_->upb_fwd;
         if (N == 1) break;
         N /= 2;
         ++l;
@@ -98,6 +99,7 @@ struct ks_plan {
     Layout lo;
     bool smoothed;
     unsigned host_flags;   // status word copied back after each call
+    int tail_passes;       // single-workgroup tail: levels needing <= this many passes
     // instrumentation (ks_time_kernels)
     int time_kind;
     bool time_armed;       // events of the current call were recorded
@@ -130,6 +132,17 @@ void collect_time(ks_plan *p) {
 
 double *seg_d(ks_plan *p, size_t off) { return reinterpret_cast<double *>(p->ws + off); }
 
+// first level whose units fit in `passes` passes of `per_pass` units
+int tail_start(const Layout &lo, int per_pass, int passes, bool backward) {
+    if (passes <= 0) return lo.L + 1;
+    for (int l = 0; l <= lo.L; ++l) {
+        const int64_t N = lo.Nl[l];
+        const int64_t units = backward ? (N + 1) / 2 : (N == 1 ? 1 : N / 2);
+        if (units <= (int64_t)per_pass * passes) return l;
+    }
+    return lo.L;
+}
+
 void enqueue_forward(ks_plan *p, const double *H, const double *F, const double *c,
                      const double *K, const double *G, const double *o, const double *C) {
     const Layout &lo = p->lo;
@@ -141,34 +154,49 @@ void enqueue_forward(ks_plan *p, const double *H, const double *F, const double 
     unsigned *flags = reinterpret_cast<unsigned *>(p->ws + lo.off_flags);
     ks::launch_clear_flags(flags, p->stream);
     mark(p, KS_TIME_FWD_ALL, 0);
-    for (int l = 0; l <= lo.L; ++l) {
-        ks::FwdArgs a{};
-        a.k = p->d.k;
+    int l0 = tail_start(lo, p->kset->upb_fwd_tail, p->tail_passes, false);
+    if (l0 > lo.L) l0 = lo.L;  // the base level always runs in the tail kernel
+    ks::FwdArgs a{};
+    a.k = p->d.k;
+    a.m = p->d.m;
+    a.K_diag = p->d.K_layout == KS_COV_DIAG;
+    a.C_diag = p->d.C_layout == KS_COV_DIAG;
+    a.H = H; a.F = F; a.c = c; a.K = K; a.G = G; a.o = o; a.C = C;
+    a.flags = flags;
+    for (int l = 0; l < l0; ++l) {
         a.Nl = lo.Nl[l];
-        a.units = lo.Nl[l] == 1 ? 1 : lo.Nl[l] / 2;
+        a.units = lo.Nl[l] / 2;
         a.level = l;
-        a.m = p->d.m;
-        a.K_diag = p->d.K_layout == KS_COV_DIAG;
-        a.C_diag = p->d.C_layout == KS_COV_DIAG;
-        a.H = H; a.F = F; a.c = c; a.K = K; a.G = G; a.o = o; a.C = C;
         a.sys_in = l >= 1 ? sys + lo.sys_off[l] : nullptr;
-        a.sys_out = l < lo.L ? sys + lo.sys_off[l + 1] : nullptr;
+        a.sys_out = sys + lo.sys_off[l + 1];
         a.rrows = rrows + lo.rec_off[l] * rrec;
         a.slots = slots + 2 * lo.slot_off[l];
-        a.flags = flags;
         if (l == 0) mark(p, KS_TIME_FWD_LEVEL0, 0);
-        if (lo.Nl[l] == 1)
-            (l == 0 ? p->kset->base_raw : p->kset->base)(a, p->stream);
-        else
-            (l == 0 ? p->kset->fwd_raw : p->kset->fwd)(a, p->stream);
+        (l == 0 ? p->kset->fwd_raw : p->kset->fwd)(a, p->stream);
         if (l == 0) mark(p, KS_TIME_FWD_LEVEL0, 1);
     }
+    ks::FwdTailArgs ta{};
+    ta.a = a;
+    ta.l0 = l0;
+    ta.L = lo.L;
+    ta.sys = sys;
+    ta.rrows = rrows;
+    ta.slots = slots;
+    ta.nprev = lo.slot_off[l0];
+    for (int l = 0; l <= lo.L; ++l) {
+        ta.sys_off[l] = lo.sys_off[l];
+        ta.rec_off[l] = lo.rec_off[l];
+        ta.Nl[l] = lo.Nl[l];
+    }
+    if (l0 == 0) mark(p, KS_TIME_FWD_LEVEL0, 0);
+    (l0 == 0 ? p->kset->fwd_tail_raw : p->kset->fwd_tail)(ta, p->stream);
+    if (l0 == 0) mark(p, KS_TIME_FWD_LEVEL0, 1);
     mark(p, KS_TIME_FWD_ALL, 1);
-    ks::launch_status(slots, lo.nslots, flags, p->stream);
 }
 
 void enqueue_backward(ks_plan *p, double *u_out, double *cov_out) {
     const Layout &lo = p->lo;
+    const int mode = (u_out && cov_out) ? ks::BWD_BOTH : (u_out ? ks::BWD_Y : ks::BWD_COV);
     ks::BwdArgs b{};
     b.k = p->d.k;
     b.rrows_all = seg_d(p, lo.off_rrows);
@@ -177,19 +205,25 @@ void enqueue_backward(ks_plan *p, double *u_out, double *cov_out) {
     b.cov = cov_out;
     b.spm = seg_d(p, lo.off_spm);
     b.spm_first = lo.spm_first;
-    for (int l = 0; l <= lo.L; ++l) b.rec_off[l] = lo.rec_off[l];
+    b.store_s = cov_out != nullptr;
+    for (int l = 0; l <= lo.L; ++l) {
+        b.rec_off[l] = lo.rec_off[l];
+        b.Nl[l] = lo.Nl[l];
+    }
+    const int l1 = tail_start(lo, p->kset->upb_bwd_tail[mode], p->tail_passes, true);
     mark(p, KS_TIME_BWD_ALL, 0);
-    for (int l = lo.L; l >= 0; --l) {
+    if (l1 <= lo.L) {
+        b.level = lo.L;
+        b.l_lo = l1;
+        if (l1 == 0) mark(p, KS_TIME_BWD_LEVEL0, 0);
+        p->kset->bwd_tail[mode](b, p->stream);
+        if (l1 == 0) mark(p, KS_TIME_BWD_LEVEL0, 1);
+    }
+    for (int l = (l1 <= lo.L ? l1 : lo.L + 1) - 1; l >= 0; --l) {
         b.level = l;
-        b.units = (lo.Nl[l] + 1) / 2;
-        b.store_s = cov_out && l >= 1;
+        b.l_lo = l;
         if (l == 0) mark(p, KS_TIME_BWD_LEVEL0, 0);
-        if (u_out && cov_out)
-            p->kset->bwd_both(b, p->stream);
-        else if (u_out)
-            p->kset->bwd_y(b, p->stream);
-        else
-            p->kset->bwd_cov(b, p->stream);
+        p->kset->bwd[mode](b, p->stream);
         if (l == 0) mark(p, KS_TIME_BWD_LEVEL0, 1);
     }
     mark(p, KS_TIME_BWD_ALL, 1);
@@ -258,6 +292,8 @@ ks_status ks_create(const ks_desc *desc, void *workspace, size_t ws_bytes, void 
     p->ev_made = false;
     p->time_ms = 0.0;
     p->time_count = 0;
+    p->tail_passes = 2;
+    if (const char *e = std::getenv("KS_TAIL_PASSES")) p->tail_passes = std::atoi(e);
     *out = p;
     return KS_OK;
 }

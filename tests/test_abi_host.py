@@ -69,7 +69,7 @@ def test_argument_errors():
     L = ks.lib()
     h = ctypes.c_void_p()
     bad = [ks.make_desc(-1, 2, 1, True, True), ks.make_desc(10, 0, 1, True, True),
-           ks.make_desc(10, 2, -1, True, True), ks.make_desc(10, 5, 3, True, True)]
+           ks.make_desc(10, 2, -1, True, True), ks.make_desc(10, 7, 3, True, True)]
     for d in bad:
         assert L.ks_workspace_bytes(ctypes.byref(d)) == 0
         assert L.ks_create(ctypes.byref(d), ctypes.c_void_p(1 << 20), 1 << 30, None, ctypes.byref(h)) == ks.KS_E_ARG

@@ -159,3 +159,21 @@ def test_errors():
         plan.covariances()
     assert e.value.status == ks.KS_E_ORDER
     plan.close()
+
+
+@pytest.mark.parametrize("k,n,m,cov", [(100, 6, 3, "dense"), (5000, 6, 3, "dense"), (777, 4, 2, "diag"),
+                                       (3000, 8, 4, "diag"), (1, 2, 1, "diag")])
+def test_tail_kernels_equal_per_level_kernels(k, n, m, cov, monkeypatch):
+    """The single-workgroup tail (top levels in one launch) computes exactly
+    what one launch per level computes."""
+    p = gen.make_problem(np.random.default_rng(k + n), k, n, m, cov=cov)
+    monkeypatch.setenv("KS_TAIL_PASSES", "0")
+    u0, S0 = gpu(p)
+    monkeypatch.setenv("KS_TAIL_PASSES", "1000000")
+    u1, S1 = gpu(p)
+    monkeypatch.delenv("KS_TAIL_PASSES")
+    u2, S2 = gpu(p)
+    assert np.array_equal(u0, u1) and np.array_equal(S0, S1)
+    assert np.array_equal(u0, u2) and np.array_equal(S0, S2)
+    ref = seq.smooth(p)
+    assert rel_u(u0, ref["u"]) < TOL_U and rel_s(S0, ref["cov"]) < TOL_S
