@@ -29,6 +29,13 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fwd_level0_n6_k100000.jso
 KERNEL_SRC = os.path.join(ROOT, "paper_2502_11686_amd", "csrc", "ks_kernels.hip")
 
 
+WORKLOAD_NAMES = {
+    0: "one trajectory, n=4, m=2, k={k}, constant F, diagonal K and C, states and covariances",
+    1: "one trajectory, n=6, m=3, k={k}, per-step F, dense K and C, states and covariances",
+    2: "one trajectory, n=48, m=24, k={k}, per-step F, diagonal K and C, states and covariances",
+}
+
+
 def level0_forward_bytes(p) -> int:
     """Algorithmic HBM bytes of the level-0 forward launch.
 
@@ -82,7 +89,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--k", type=int, default=100000)
+    ap.add_argument("--workload", type=int, default=1, choices=(0, 1, 2))
+    ap.add_argument("--k", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     args = ap.parse_args()
@@ -96,7 +104,7 @@ def main():
 
     from paper_2502_11686_amd import gen, ks
 
-    p = gen.workload(1, k=args.k)
+    p = gen.workload(args.workload, k=args.k)
     dev = torch.device("cuda", 0)
     tens = ks.to_device(p, dev)
     plan = ks.Plan(p.k, p.n, p.m, p.K_diag, p.C_diag, device=dev)
@@ -165,8 +173,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic (seeded generator; per-step Haar-based F, Gaussian G, dense SPD K and C)",
-        "config": {"workload": "one trajectory, n=6, m=3, k=100000, per-step F, dense K and C, "
-                               "states and covariances", "problems": 1, "k": p.k, "n": p.n, "m": p.m},
+        "config": {"workload": WORKLOAD_NAMES[args.workload].format(k=p.k), "problems": 1,
+                   "k": p.k, "n": p.n, "m": p.m},
         "p50_ms": float(np.percentile(lat_ms, 50)),
         "p99_ms": float(np.percentile(lat_ms, 99)),
         "nc_value": (p.k + 1) * nc_steps / nc_el,
@@ -174,7 +182,7 @@ def main():
         "err_vs_oracle": err,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_forward<6,3,raw> (level 0)", "algo_bytes_per_launch": algo,
+                     "kernel": f"level-0 forward (n={p.n}, m={p.m})", "algo_bytes_per_launch": algo,
                      "avg_launch_ms": avg_s * 1e3, "launches_timed": k_cnt},
     }
     if not args.no_cpu_baseline:

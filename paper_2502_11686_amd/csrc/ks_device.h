@@ -1,4 +1,6 @@
-// ks_kernels.hip -- gfx950 kernels of the odd-even Kalman smoother.
+#pragma once
+// ks_device.h -- gfx950 kernels of the odd-even Kalman smoother (templates;
+// instantiated per state dimension by the ks_inst_*.hip translation units).
 //
 // Forward (Section III): one launch per level l.  The level-l system has N_l
 // block columns; column j carries an observation-like block (O_j | w_j) and,
@@ -45,7 +47,7 @@
 
 namespace ks {
 
-enum Role { CUR = 0, RIGHT = 1, RHS = 2, LEFT = 3, IDLE = 4 };
+enum Role { CUR = 0, RIGHT = 1, RHS = 2, LEFT = 3, IDLE = 4, BRIGHT = 5, BRHS = 6 };
 
 template <int N>
 struct Geo {
@@ -207,19 +209,19 @@ __device__ __forceinline__ void whiten_diag(double (&x)[H], int roff, const doub
 // ---------------------------------------------------------------- loaders
 
 // observation block of a reduced-system column, rows [O | w], onto owner lanes
-template <int N, int H>
+template <int N, int H, class LR>
 __device__ __forceinline__ void load_obs_sys(double (&x)[H], int roff, const double *obs,
-                                             const LaneRole<N> &L, int own, bool valid) {
-    const int col = (L.role == own) ? L.rc : (L.role == RHS ? N : -1);
+                                             const LR &L, int own, bool valid, int rhs = RHS) {
+    const int col = (L.role == own) ? L.rc : (L.role == rhs ? N : -1);
     const bool ld = valid && col >= 0;
 #pragma unroll
     for (int r = 0; r < N; ++r) x[roff + r] = ld ? obs[r * (N + 1) + col] : 0.0;
 }
 
 // evolution block of a reduced-system column, rows [E- | E+ | eta]
-template <int N, int H>
+template <int N, int H, class LR>
 __device__ __forceinline__ void load_evol_sys(double (&x)[H], int roff, const double *ev,
-                                              const LaneRole<N> &L, int role_m, int role_p,
+                                              const LR &L, int role_m, int role_p,
                                               bool valid) {
     const int col = L.role == role_m ? L.rc
                   : L.role == role_p ? N + L.rc
@@ -232,12 +234,13 @@ __device__ __forceinline__ void load_evol_sys(double (&x)[H], int roff, const do
 // Raw observation step j, rows [G_j | o_j] (m rows, zero rows up to MM), and
 // the covariance data for its whitening: cv = column (gl - cl0) of C_j on the
 // lanes cl0 .. cl0+MM-1 (identity columns for padding rows), or the variances.
-template <int N, int MM, int H>
+template <int N, int MM, int H, class LR>
 __device__ __forceinline__ void load_obs_raw(double (&x)[H], int roff, double (&cv)[MM],
-                                             int64_t j, const LaneRole<N> &L, int gl, int own,
-                                             int cl0, const FwdArgs &a, bool valid) {
+                                             int64_t j, const LR &L, int gl, int own,
+                                             int cl0, const FwdArgs &a, bool valid,
+                                             int rhs = RHS) {
     const int m = a.m;
-    const int col = (L.role == own) ? L.rc : (L.role == RHS ? N : -1);
+    const int col = (L.role == own) ? L.rc : (L.role == rhs ? N : -1);
     const bool ld = valid && col >= 0;
     const double *Gj = a.G + j * (int64_t)m * N;
     const double *oj = a.o + j * (int64_t)m;
@@ -260,9 +263,9 @@ __device__ __forceinline__ void load_obs_raw(double (&x)[H], int roff, double (&
 
 // Raw evolution step i (1..k), rows [-F_i | H_i | c_i] (zero block when
 // !valid), with its covariance data as in load_obs_raw.
-template <int N, int H>
+template <int N, int H, class LR>
 __device__ __forceinline__ void load_evol_raw(double (&x)[H], int roff, double (&cv)[N], int64_t i,
-                                              const LaneRole<N> &L, int gl, int role_m,
+                                              const LR &L, int gl, int role_m,
                                               int role_p, int cl0, const FwdArgs &a, bool valid) {
     const int64_t t = i - 1;  // ABI entry of step i
     const double *F = a.F + t * N * N;
@@ -303,8 +306,8 @@ __device__ __forceinline__ void whiten(bool diag, double (&x)[H], int roff, doub
 
 // ------------------------------------------------------ shared epilogues
 
-template <int N, int H>
-__device__ __forceinline__ void diag_stats(const double (&x)[H], const LaneRole<N> &L, bool valid,
+template <int N, int H, class LR>
+__device__ __forceinline__ void diag_stats(const double (&x)[H], const LR &L, bool valid,
                                            double &dmin, double &dmax, bool &nonfinite) {
     if (!valid || L.role != CUR) return;
     double d = 0.0;
@@ -355,9 +358,55 @@ __device__ __forceinline__ void store_rrow(double *rec, const double (&x)[H], in
 
 // ------------------------------------------------------------- forward level
 
-// One unit of a forward level: even column j = 2t and its right neighbour
-// (plus the last column when it is the folding unit).  No workgroup barrier.
+// The last column jl = N_l - 1 of a level with N_l odd (even, no right
+// neighbour): its R row (record t+1), and its Z rows, which touch only column
+// jl - 1, stacked under the step-3 triangle Onew of the last unit t.
 template <int N, int MM, bool RAW>
+__device__ __forceinline__ void fold_part(const FwdArgs &a, int64_t t, int gl, int gb,
+                                          const LaneRole<N> &L, double (&Onew)[N], double &dmin,
+                                          double &dmax, bool &bad, bool &nonfinite) {
+    using GE = Geo<N>;
+    constexpr int RO = RAW ? MM : N;
+    constexpr int HC = 2 * N;
+    // the last column jl = N_l - 1 (even, no right neighbour)
+    const int64_t jl = a.Nl - 1;
+    double A2[RO], C2[HC];
+#pragma unroll
+    for (int r = N; r < HC; ++r) C2[r] = 0.0;
+    if constexpr (RAW) {
+        double cvO[MM], cvE[N];
+        load_obs_raw<N, MM>(A2, 0, cvO, jl, L, gl, CUR, 0, a, true);
+        load_evol_raw<N>(C2, 0, cvE, jl, L, gl, LEFT, CUR, 2 * N + 1, a, true);
+        whiten<RO, MM>(a.C_diag, A2, 0, cvO, gl, gb, 0, bad);
+        whiten<HC, N>(a.K_diag, C2, 0, cvE, gl, gb, 2 * N + 1, bad);
+    } else {
+        load_obs_sys<N>(A2, 0, a.sys_in + jl * GE::SREC, L, CUR, true);
+        load_evol_sys<N>(C2, 0, a.sys_in + jl * GE::SREC + GE::OREC, L, LEFT, CUR, true);
+    }
+    hqr<RO, N>(A2, gl, gb, 0);
+#pragma unroll
+    for (int r = 0; r < N; ++r) C2[N + r] = r < RO ? A2[r] : 0.0;
+    hqr<HC, N>(C2, gl, gb, 0);
+    store_rrow<N>(a.rrows + (t + 1) * GE::RREC, C2, gl, true);
+    diag_stats<N>(C2, L, true, dmin, dmax, nonfinite);
+    // Z rows (left lanes) move onto the right lanes; rhs keeps zeta
+    const int src = gb + ((L.role == RIGHT) ? gl + N + 1 : gl);
+    double B2[2 * N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        const double z = bperm(C2[N + r], src);
+        B2[r] = Onew[r];
+        B2[N + r] = (L.role == RIGHT || L.role == RHS) ? z : 0.0;
+    }
+    hqr<2 * N, N>(B2, gl, gb, N);
+#pragma unroll
+    for (int r = 0; r < N; ++r) Onew[r] = B2[r];
+}
+
+// One unit of a forward level: even column j = 2t and its right neighbour
+// (plus, with INLINE_FOLD, the last column when it is the folding unit; the
+// per-level kernels leave that to k_fold).  No workgroup barrier.
+template <int N, int MM, bool RAW, bool INLINE_FOLD>
 __device__ __forceinline__ void fwd_unit(const FwdArgs &a, int64_t t, bool in, int gl, int gb,
                                          double &dmin, double &dmax, bool &bad, bool &nonfinite) {
     using GE = Geo<N>;
@@ -421,41 +470,7 @@ __device__ __forceinline__ void fwd_unit(const FwdArgs &a, int64_t t, bool in, i
 #pragma unroll
     for (int r = 0; r < N; ++r) Onew[r] = r < PB ? B[r] : 0.0;
 
-    if (fold) {
-        // the last column jl = N_l - 1 (even, no right neighbour)
-        const int64_t jl = a.Nl - 1;
-        double A2[RO], C2[HC];
-#pragma unroll
-        for (int r = N; r < HC; ++r) C2[r] = 0.0;
-        if constexpr (RAW) {
-            double cvO[MM], cvE[N];
-            load_obs_raw<N, MM>(A2, 0, cvO, jl, L, gl, CUR, 0, a, true);
-            load_evol_raw<N>(C2, 0, cvE, jl, L, gl, LEFT, CUR, 2 * N + 1, a, true);
-            whiten<RO, MM>(a.C_diag, A2, 0, cvO, gl, gb, 0, bad);
-            whiten<HC, N>(a.K_diag, C2, 0, cvE, gl, gb, 2 * N + 1, bad);
-        } else {
-            load_obs_sys<N>(A2, 0, a.sys_in + jl * GE::SREC, L, CUR, true);
-            load_evol_sys<N>(C2, 0, a.sys_in + jl * GE::SREC + GE::OREC, L, LEFT, CUR, true);
-        }
-        hqr<RO, N>(A2, gl, gb, 0);
-#pragma unroll
-        for (int r = 0; r < N; ++r) C2[N + r] = r < RO ? A2[r] : 0.0;
-        hqr<HC, N>(C2, gl, gb, 0);
-        store_rrow<N>(a.rrows + (t + 1) * GE::RREC, C2, gl, true);
-        diag_stats<N>(C2, L, true, dmin, dmax, nonfinite);
-        // Z rows (left lanes) move onto the right lanes; rhs keeps zeta
-        const int src = gb + ((L.role == RIGHT) ? gl + N + 1 : gl);
-        double B2[2 * N];
-#pragma unroll
-        for (int r = 0; r < N; ++r) {
-            const double z = bperm(C2[N + r], src);
-            B2[r] = Onew[r];
-            B2[N + r] = (L.role == RIGHT || L.role == RHS) ? z : 0.0;
-        }
-        hqr<2 * N, N>(B2, gl, gb, N);
-#pragma unroll
-        for (int r = 0; r < N; ++r) Onew[r] = B2[r];
-    }
+    if (INLINE_FOLD && fold) fold_part<N, MM, RAW>(a, t, gl, gb, L, Onew, dmin, dmax, bad, nonfinite);
 
     // reduced column t, observation block from step 3 (with the fold, if any)
     if (valid) {
@@ -523,11 +538,43 @@ __global__ __launch_bounds__(kBlock) void k_forward(FwdArgs a) {
     bool bad = false, nonfinite = false;
     double dmin = INFINITY, dmax = 0.0;
     const int64_t t = (int64_t)blockIdx.x * Geo<N>::UPB + g.ui;
-    fwd_unit<N, MM, RAW>(a, t, g.in, g.gl, g.gbase, dmin, dmax, bad, nonfinite);
+    fwd_unit<N, MM, RAW, false>(a, t, g.in, g.gl, g.gbase, dmin, dmax, bad, nonfinite);
     block_minmax<kBlock>(dmin, dmax, bad, nonfinite, a.flags);
     if (threadIdx.x == 0) {
         a.slots[2 * blockIdx.x] = dmin;
         a.slots[2 * blockIdx.x + 1] = dmax;
+    }
+}
+
+// The fold of a level with N_l odd, after that level's k_forward: one unit
+// reloads the last unit's step-3 triangle, eliminates the last column and
+// re-triangularizes.  Writes one slot (a.fold_slot).
+template <int N, int MM, bool RAW>
+__global__ __launch_bounds__(kBlock) void k_fold(FwdArgs a) {
+    using GE = Geo<N>;
+    const Grp<N> g;
+    const bool valid = g.in && g.ui == 0;
+    const LaneRole<N> L(g.gl);
+    bool bad = false, nonfinite = false;
+    double dmin = INFINITY, dmax = 0.0;
+    const int64_t t = a.units - 1;
+    if (g.ui == 0) {  // one unit: lanes of the other units stay idle
+        double Onew[N];
+        load_obs_sys<N>(Onew, 0, a.sys_out + t * GE::SREC, L, RIGHT, valid);
+        fold_part<N, MM, RAW>(a, t, g.gl, g.gbase, L, Onew, dmin, dmax, bad, nonfinite);
+        if (valid) {
+            const int oc = L.role == RIGHT ? L.rc : (L.role == RHS ? N : -1);
+            if (oc >= 0) {
+                double *rec = a.sys_out + t * GE::SREC;
+#pragma unroll
+                for (int r = 0; r < N; ++r) rec[r * (N + 1) + oc] = Onew[r];
+            }
+        }
+    }
+    block_minmax<kBlock>(dmin, dmax, bad, nonfinite, a.flags);
+    if (threadIdx.x == 0) {
+        a.fold_slot[0] = dmin;
+        a.fold_slot[1] = dmax;
     }
 }
 
@@ -558,9 +605,9 @@ __global__ __launch_bounds__(kTailBlock) void k_fwd_tail(FwdTailArgs ta) {
         } else {
             for (int64_t t0 = 0; t0 < a.units; t0 += UPB) {
                 if (RAW0 && l == 0)
-                    fwd_unit<N, MM, true>(a, t0 + g.ui, g.in, g.gl, g.gbase, dmin, dmax, bad, nonfinite);
+                    fwd_unit<N, MM, true, true>(a, t0 + g.ui, g.in, g.gl, g.gbase, dmin, dmax, bad, nonfinite);
                 else
-                    fwd_unit<N, MM, false>(a, t0 + g.ui, g.in, g.gl, g.gbase, dmin, dmax, bad, nonfinite);
+                    fwd_unit<N, MM, false, true>(a, t0 + g.ui, g.in, g.gl, g.gbase, dmin, dmax, bad, nonfinite);
             }
         }
         __threadfence();
@@ -777,16 +824,6 @@ __global__ __launch_bounds__(TB) void k_bwd_tail(BwdArgs a) {
     }
 }
 
-// ----------------------------------------------------------------- status
-
-__global__ void k_clear_flags(unsigned *flags) {
-    if (threadIdx.x == 0) flags[0] = 0u;
-}
-
-void launch_clear_flags(unsigned *flags, hipStream_t s) {
-    hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(64), 0, s, flags);
-}
-
 // -------------------------------------------------------------- dispatch
 
 template <int N, bool Y, bool COV>
@@ -800,6 +837,11 @@ template <int N, int MM, bool RAW>
 static void launch_fwd_t(const FwdArgs &a, hipStream_t s) {
     const int64_t blocks = (a.units + Geo<N>::UPB - 1) / Geo<N>::UPB;
     hipLaunchKernelGGL((k_forward<N, MM, RAW>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
+}
+
+template <int N, int MM, bool RAW>
+static void launch_fold_t(const FwdArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL((k_fold<N, MM, RAW>), dim3(1), dim3(kBlock), 0, s, a);
 }
 
 template <int N, int MM, bool RAW0>
@@ -821,11 +863,13 @@ static void launch_bwd_tail_t(const BwdArgs &a, hipStream_t s) {
 }
 
 template <int N, int MM>
-static constexpr KernelSet make_set() {
+constexpr KernelSet make_set() {
     return KernelSet{N,
                      MM,
                      &launch_fwd_t<N, MM, true>,
                      &launch_fwd_t<N, MM, false>,
+                     &launch_fold_t<N, MM, true>,
+                     &launch_fold_t<N, MM, false>,
                      &launch_fwd_tail_t<N, MM, true>,
                      &launch_fwd_tail_t<N, MM, false>,
                      {&launch_bwd_t<N, true, false>, &launch_bwd_t<N, false, true>,
@@ -841,19 +885,5 @@ static constexpr KernelSet make_set() {
 }
 
 #define KS_SETS(N) make_set<N, (N + 1) / 2>(), make_set<N, N>(), make_set<N, 2 * N>()
-
-static const KernelSet kSets[] = {
-    make_set<1, 1>(), make_set<1, 2>(), KS_SETS(2), KS_SETS(3), KS_SETS(4), KS_SETS(5),
-    KS_SETS(6),       KS_SETS(8),
-};
-
-const KernelSet *find_kernels(int n, int m) {
-    const KernelSet *best = nullptr;
-    for (const KernelSet &s : kSets) {
-        if (s.n != n || s.mm < (m > 0 ? m : 1)) continue;
-        if (!best || s.mm < best->mm) best = &s;
-    }
-    return best;
-}
 
 }  // namespace ks

@@ -1,0 +1,15 @@
+// ks_inst_blk_n24.hip -- workgroup-family kernel instantiations for n = 24.
+#include "ks_device_blk.h"
+
+namespace ks {
+
+// host-only table (a function-local static is never emitted for the device)
+const KernelSetList &list_blk_n24() {
+    static const KernelSet sets[] = {
+    KS_BLK_SETS(24),
+    };
+    static const KernelSetList list = {sets, sizeof(sets) / sizeof(sets[0])};
+    return list;
+}
+
+}  // namespace ks

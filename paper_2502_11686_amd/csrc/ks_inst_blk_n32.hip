@@ -1,0 +1,15 @@
+// ks_inst_blk_n32.hip -- workgroup-family kernel instantiations for n = 32.
+#include "ks_device_blk.h"
+
+namespace ks {
+
+// host-only table (a function-local static is never emitted for the device)
+const KernelSetList &list_blk_n32() {
+    static const KernelSet sets[] = {
+    KS_BLK_SETS(32),
+    };
+    static const KernelSetList list = {sets, sizeof(sets) / sizeof(sets[0])};
+    return list;
+}
+
+}  // namespace ks

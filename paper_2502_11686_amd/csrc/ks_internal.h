@@ -34,6 +34,7 @@ struct FwdArgs {
     double *sys_out;
     double *rrows;    // first R-row record of this level
     double *slots;    // per-block [min |R_pp|, max |R_pp|]
+    double *fold_slot;  // [min, max] of the level's fold kernel
     unsigned *flags;
 };
 
@@ -74,6 +75,8 @@ struct KernelSet {
     int n, mm;
     void (*fwd_raw)(const FwdArgs &, hipStream_t);
     void (*fwd)(const FwdArgs &, hipStream_t);
+    void (*fold_raw)(const FwdArgs &, hipStream_t);   // last column of an odd level
+    void (*fold)(const FwdArgs &, hipStream_t);
     void (*fwd_tail_raw)(const FwdTailArgs &, hipStream_t);  // tail starting at level 0
     void (*fwd_tail)(const FwdTailArgs &, hipStream_t);
     void (*bwd[3])(const BwdArgs &, hipStream_t);             // indexed by BwdMode
@@ -82,6 +85,11 @@ struct KernelSet {
     int upb_fwd_tail;     // units per pass of the forward tail
     int upb_bwd[3];
     int upb_bwd_tail[3];
+};
+
+struct KernelSetList {
+    const KernelSet *sets;
+    int64_t count;
 };
 
 // nullptr when (n, m) has no instantiation

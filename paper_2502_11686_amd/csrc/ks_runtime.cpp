@@ -65,7 +65,8 @@ bool make_layout(const ks_desc *d, const ks::KernelSet *ks_, Layout *lo) {
         }
         rec += (N + 1) / 2;
         const int64_t units = N == 1 ? 1 : N / 2;
-        slots += N == 1 ? 1 : (units + ks_->upb_fwd - 1) / ks_->upb_fwd;
+        // per-block slots of the level kernel, plus one for the fold kernel of an odd level
+        slots += N == 1 ? 1 : (units + ks_->upb_fwd - 1) / ks_->upb_fwd + (N & 1);
         if (N == 1) break;
         N /= 2;
         ++l;
@@ -171,8 +172,11 @@ void enqueue_forward(ks_plan *p, const double *H, const double *F, const double 
         a.sys_out = sys + lo.sys_off[l + 1];
         a.rrows = rrows + lo.rec_off[l] * rrec;
         a.slots = slots + 2 * lo.slot_off[l];
+        const int64_t blocks = (a.units + p->kset->upb_fwd - 1) / p->kset->upb_fwd;
+        a.fold_slot = a.slots + 2 * blocks;
         if (l == 0) mark(p, KS_TIME_FWD_LEVEL0, 0);
         (l == 0 ? p->kset->fwd_raw : p->kset->fwd)(a, p->stream);
+        if (lo.Nl[l] & 1) (l == 0 ? p->kset->fold_raw : p->kset->fold)(a, p->stream);
         if (l == 0) mark(p, KS_TIME_FWD_LEVEL0, 1);
     }
     ks::FwdTailArgs ta{};

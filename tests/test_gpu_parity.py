@@ -40,14 +40,17 @@ def gpu(p, mode="fused"):
         plan.close()
 
 
-SHAPES = [(1, 1), (2, 1), (4, 2), (3, 3), (6, 3), (4, 5), (8, 4), (2, 4), (6, 6), (3, 1)]
+SHAPES = [(1, 1), (2, 1), (4, 2), (3, 3), (6, 3), (4, 5), (8, 4), (2, 4), (6, 6), (3, 1), (5, 3),
+          (12, 6), (16, 8), (12, 12)]
+LARGE = [(24, 12), (32, 16), (48, 24), (24, 24)]
 KS = list(range(0, 20)) + [31, 32, 33, 63, 64, 100, 127, 128, 129]
+KS_LARGE = [0, 1, 2, 3, 4, 5, 6, 7, 8, 15, 16, 17, 31, 33, 64]
 
 
-@pytest.mark.parametrize("n,m", SHAPES)
+@pytest.mark.parametrize("n,m", SHAPES + LARGE)
 def test_small_sweep(n, m):
     worst = [0.0, 0.0]
-    for k in KS:
+    for k in (KS if n <= 16 else KS_LARGE):
         if (k + 1) * m < n:
             continue  # fewer observation rows than unknowns beyond the evolution rows: rank deficient
         for cov in ("diag", "dense"):
@@ -63,7 +66,7 @@ def test_small_sweep(n, m):
     print(f"n={n} m={m}: worst state {worst[0]:.2e}, cov {worst[1]:.2e}", flush=True)
 
 
-@pytest.mark.parametrize("wid", [0, 1])
+@pytest.mark.parametrize("wid", [0, 1, 2])
 def test_full_workloads(wid):
     p = gen.workload(wid)
     print(f"workload {wid}: k={p.k} n={p.n} m={p.m}", flush=True)
