@@ -26,7 +26,8 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fwd_level0_n6_k100000.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2502_11686_amd", "csrc", "ks_kernels.hip")
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2502_11686_amd", "csrc", f)
+               for f in ("ks_device.h", "ks_device_blk.h", "ks_internal.h")]
 
 
 WORKLOAD_NAMES = {
@@ -54,7 +55,10 @@ def level0_forward_bytes(p) -> int:
 
 
 def kernel_source_hash() -> str:
-    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in KERNEL_SRCS:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(per_launch_algo: int):
@@ -145,15 +149,40 @@ def main():
         phases[name] = round(ms / max(cnt, 1), 4)
     plan.time_kernels(ks.KS_TIME_OFF)
 
+    def errors(ref):
+        uu, SS = u.cpu().numpy(), S.cpu().numpy()
+        return dict(state=float(np.max(np.abs(uu - ref["u"])) / np.max(np.abs(ref["u"]))),
+                    cov=float(np.max(np.linalg.norm(SS - ref["cov"], axis=(1, 2)) /
+                                     np.linalg.norm(ref["cov"], axis=(1, 2)))))
+
+    ref = None
     err = None
     if not args.no_check:
         from oracle import seq
         ref = seq.smooth(p)
         plan.smooth_cov(*tens, u_out=u, cov_out=S)
-        uu, SS = u.cpu().numpy(), S.cpu().numpy()
-        err = dict(state=float(np.max(np.abs(uu - ref["u"])) / np.max(np.abs(ref["u"]))),
-                   cov=float(np.max(np.linalg.norm(SS - ref["cov"], axis=(1, 2)) /
-                                    np.linalg.norm(ref["cov"], axis=(1, 2)))))
+        err = errors(ref)
+
+    # the FP32 form on the same inputs (FP32 wide levels, FP64 top levels and SelInv)
+    plan32 = ks.Plan(p.k, p.n, p.m, p.K_diag, p.C_diag, device=dev, fp32=True)
+    for _ in range(max(1, args.warmup // 2)):
+        plan32.smooth_cov(*tens, u_out=u, cov_out=S)
+    steps32 = max(10, args.steps // 2)
+    lat32 = []
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(steps32):
+        ts = time.perf_counter()
+        plan32.smooth_cov(*tens, u_out=u, cov_out=S)
+        lat32.append(time.perf_counter() - ts)
+    torch.cuda.synchronize()
+    el32 = time.perf_counter() - t2
+    fp32_form = dict(value=(p.k + 1) * steps32 / el32, unit="steps/s",
+                     ms_per_step=el32 / steps32 * 1e3,
+                     p50_ms=float(np.percentile(np.array(lat32) * 1e3, 50)),
+                     p99_ms=float(np.percentile(np.array(lat32) * 1e3, 99)),
+                     err_vs_oracle=errors(ref) if ref is not None else None)
+    plan32.close()
 
     algo = level0_forward_bytes(p)
     avg_s = (k_ms / max(k_cnt, 1)) / 1e3
@@ -180,6 +209,7 @@ def main():
         "nc_value": (p.k + 1) * nc_steps / nc_el,
         "phase_ms": phases,
         "err_vs_oracle": err,
+        "fp32_form": fp32_form,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": f"level-0 forward (n={p.n}, m={p.m})", "algo_bytes_per_launch": algo,

@@ -67,7 +67,17 @@ typedef enum {
     KS_E_ORDER = -7         /* ks_covariances before a successful ks_smooth                */
 } ks_status;
 
-typedef enum { KS_FP64 = 0 } ks_precision;
+/* KS_FP64: every level in FP64.
+ * KS_FP32_FORM: the elimination levels with more than 1024 block columns
+ * (the wide bottom of the recursion, where almost all the work and traffic
+ * is) run in FP32 with FP32 accumulation -- column norms of the Householder
+ * vectors scaled by the column's largest entry, reflector coefficients from
+ * refined reciprocals -- and keep their R rows and reduced systems in FP32;
+ * the top levels run in FP64, and back-substitution and every SelInv product
+ * (R^{-1} R^{-T}, T S T^T) run in FP64 on the FP32 rows.  Inputs and outputs
+ * stay FP64.  The rank test uses 64 FLT_EPSILON.  (The switch point can be
+ * moved with the environment variable KS_FP32_SWITCH read at ks_create.) */
+typedef enum { KS_FP64 = 0, KS_FP32_FORM = 1 } ks_precision;
 typedef enum { KS_COV_DENSE = 0, KS_COV_DIAG = 1 } ks_cov_layout;
 
 /* Problem description.  k >= 0 evolution steps (k + 1 states), state

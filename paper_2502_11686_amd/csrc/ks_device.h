@@ -99,7 +99,33 @@ __device__ __forceinline__ double bperm(double v, int src) {
     return __hiloint2double(hi, lo);
 }
 
-// 1/d and 1/sqrt(d) from the hardware estimates refined by two Newton steps
+__device__ __forceinline__ float bperm(float v, int src) {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
+}
+
+template <class T>
+struct Num;
+template <>
+struct Num<double> {
+    static constexpr double eps = 2.220446049250313e-16;
+};
+template <>
+struct Num<float> {
+    static constexpr double eps = 1.1920928955078125e-07;
+};
+
+// 1/d and 1/sqrt(d) from the hardware estimates refined by Newton steps
+// (two in FP64, one in FP32)
+__device__ __forceinline__ float rcp_nr(float d) {
+    const float r = __builtin_amdgcn_rcpf(d);
+    return fmaf(r, fmaf(-d, r, 1.0f), r);
+}
+
+__device__ __forceinline__ float rsq_nr(float d) {
+    const float r = __builtin_amdgcn_rsqf(d);
+    return r * fmaf(-0.5f * d * r, r, 1.5f);
+}
+
 __device__ __forceinline__ double rcp_nr(double d) {
     double r = __builtin_amdgcn_rcp(d);
     r = fma(r, fma(-d, r, 1.0), r);
@@ -123,37 +149,51 @@ __device__ __forceinline__ double rsq_nr(double d) {
 // reflector to its own column (the pivot lane too); the pivot diagonal is then
 // set to beta and, at the end, the strictly lower parts of the pivot columns
 // are set to zero.
-template <int H, int NP>
-__device__ __forceinline__ void hqr(double (&x)[H], int gl, int gbase, int pl0) {
+template <int H, int NP, class T>
+__device__ __forceinline__ void hqr(T (&x)[H], int gl, int gbase, int pl0) {
     constexpr int P = NP < H ? NP : H;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
         const int src = gbase + pl0 + p;
-        const double alpha = x[p];
-        double s0 = 0.0, s1 = 0.0;
+        const T alpha = x[p];
+        T s0 = 0, s1 = 0, sc = 1, am = 1, as = alpha;
+        if constexpr (sizeof(T) == 4) {
+            // FP32: sum of squares of the column scaled by its largest entry
+            // (no overflow or underflow for any representable column)
+            am = fabs(alpha);
 #pragma unroll
-        for (int r = p + 1; r < H; r += 2) s0 = fma(x[r], x[r], s0);
+            for (int r = p + 1; r < H; ++r) am = fmax(am, fabs(x[r]));
+            sc = am > T(0) ? rcp_nr(am) : T(0);
+            as = alpha * sc;
 #pragma unroll
-        for (int r = p + 2; r < H; r += 2) s1 = fma(x[r], x[r], s1);
-        const double xn2 = s0 + s1;
-        const double s = fma(alpha, alpha, xn2);
-        const double nrm = sqrt(s);
-        const double beta = -copysign(nrm, alpha);
-        const bool nz = xn2 != 0.0;
-        const double cc = nz ? rcp_nr(fma(fabs(alpha), nrm, s)) : 0.0;
-        const double v0 = alpha - beta;
-        const double dnew = nz ? beta : alpha;
-        const double cb = bperm(cc, src);
-        const double v0b = bperm(v0, src);
-        double v[H];
+            for (int r = p + 1; r < H; r += 2) s0 = fma(x[r] * sc, x[r] * sc, s0);
+#pragma unroll
+            for (int r = p + 2; r < H; r += 2) s1 = fma(x[r] * sc, x[r] * sc, s1);
+        } else {
+#pragma unroll
+            for (int r = p + 1; r < H; r += 2) s0 = fma(x[r], x[r], s0);
+#pragma unroll
+            for (int r = p + 2; r < H; r += 2) s1 = fma(x[r], x[r], s1);
+        }
+        const T xn2 = s0 + s1;                       // scaled by sc^2 in FP32
+        const T s = fma(as, as, xn2);
+        const T nrs = sqrt(s);                       // ||x_{p:}|| * sc
+        const bool nz = xn2 != T(0);
+        const T beta = -copysign(nrs * am, alpha);
+        const T cc = nz ? sc * sc * rcp_nr(fma(fabs(as), nrs, s)) : T(0);
+        const T v0 = alpha - beta;
+        const T dnew = nz ? beta : alpha;
+        const T cb = bperm(cc, src);
+        const T v0b = bperm(v0, src);
+        T v[H];
 #pragma unroll
         for (int r = p + 1; r < H; ++r) v[r] = bperm(x[r], src);
-        double w0 = v0b * x[p], w1 = 0.0;
+        T w0 = v0b * x[p], w1 = 0;
 #pragma unroll
         for (int r = p + 1; r < H; r += 2) w0 = fma(v[r], x[r], w0);
 #pragma unroll
         for (int r = p + 2; r < H; r += 2) w1 = fma(v[r], x[r], w1);
-        const double w = (w0 + w1) * cb;
+        const T w = (w0 + w1) * cb;
         x[p] = (gl == pl0 + p) ? dnew : fma(-w, v0b, x[p]);
 #pragma unroll
         for (int r = p + 1; r < H; ++r) x[r] = fma(-w, v[r], x[r]);
@@ -161,7 +201,7 @@ __device__ __forceinline__ void hqr(double (&x)[H], int gl, int gbase, int pl0) 
     const unsigned q = (unsigned)(gl - pl0);
 #pragma unroll
     for (int r = 1; r < H; ++r)
-        if (q < (unsigned)(r < P ? r : P)) x[r] = 0.0;
+        if (q < (unsigned)(r < P ? r : P)) x[r] = T(0);
 }
 
 // Whitening by a dense SPD covariance (Section II-A): rows roff..roff+D-1 of
@@ -171,23 +211,23 @@ __device__ __forceinline__ void hqr(double (&x)[H], int gl, int gbase, int pl0) 
 // lanes (each keeps its column of the symmetric Schur complement, so
 // L(q,p) = cv_q[p] / L(p,p) is local) and is fused with the forward
 // substitution, one broadcast column of L per pivot.
-template <int H, int D>
-__device__ __forceinline__ void whiten_dense(double (&x)[H], int roff, double (&cv)[D], int gl,
+template <int H, int D, class T>
+__device__ __forceinline__ void whiten_dense(T (&x)[H], int roff, T (&cv)[D], int gl,
                                              int gbase, int cl0, bool &bad) {
 #pragma unroll
     for (int p = 0; p < D; ++p) {
         const int src = gbase + cl0 + p;
-        const double piv = cv[p];
-        if (gl == cl0 + p && !(piv > 0.0 && isfinite(piv))) bad = true;
-        const double il = rsq_nr(piv);
-        const double ilb = bperm(il, src);
-        double lb[D];
+        const T piv = cv[p];
+        if (gl == cl0 + p && !(piv > T(0) && isfinite(piv))) bad = true;
+        const T il = rsq_nr(piv);
+        const T ilb = bperm(il, src);
+        T lb[D];
 #pragma unroll
         for (int r = p + 1; r < D; ++r) lb[r] = bperm(cv[r] * il, src);
-        const double f = cv[p] * ilb;
+        const T f = cv[p] * ilb;
 #pragma unroll
         for (int r = p + 1; r < D; ++r) cv[r] = fma(-lb[r], f, cv[r]);
-        const double xp = x[roff + p] * ilb;
+        const T xp = x[roff + p] * ilb;
         x[roff + p] = xp;
 #pragma unroll
         for (int r = p + 1; r < D; ++r) x[roff + r] = fma(-lb[r], xp, x[roff + r]);
@@ -195,13 +235,13 @@ __device__ __forceinline__ void whiten_dense(double (&x)[H], int roff, double (&
 }
 
 // Whitening by a diagonal covariance: row r scaled by 1/sqrt(var_r).
-template <int H, int D>
-__device__ __forceinline__ void whiten_diag(double (&x)[H], int roff, const double (&var)[D],
+template <int H, int D, class T>
+__device__ __forceinline__ void whiten_diag(T (&x)[H], int roff, const T (&var)[D],
                                             int gl, bool &bad) {
 #pragma unroll
     for (int r = 0; r < D; ++r) {
-        const double v = var[r];
-        if (gl == 0 && !(v > 0.0 && isfinite(v))) bad = true;
+        const T v = var[r];
+        if (gl == 0 && !(v > T(0) && isfinite(v))) bad = true;
         x[roff + r] *= rsq_nr(v);
     }
 }
@@ -209,18 +249,18 @@ __device__ __forceinline__ void whiten_diag(double (&x)[H], int roff, const doub
 // ---------------------------------------------------------------- loaders
 
 // observation block of a reduced-system column, rows [O | w], onto owner lanes
-template <int N, int H, class LR>
-__device__ __forceinline__ void load_obs_sys(double (&x)[H], int roff, const double *obs,
+template <int N, int H, class LR, class T, class TIN>
+__device__ __forceinline__ void load_obs_sys(T (&x)[H], int roff, const TIN *obs,
                                              const LR &L, int own, bool valid, int rhs = RHS) {
     const int col = (L.role == own) ? L.rc : (L.role == rhs ? N : -1);
     const bool ld = valid && col >= 0;
 #pragma unroll
-    for (int r = 0; r < N; ++r) x[roff + r] = ld ? obs[r * (N + 1) + col] : 0.0;
+    for (int r = 0; r < N; ++r) x[roff + r] = ld ? T(obs[r * (N + 1) + col]) : T(0);
 }
 
 // evolution block of a reduced-system column, rows [E- | E+ | eta]
-template <int N, int H, class LR>
-__device__ __forceinline__ void load_evol_sys(double (&x)[H], int roff, const double *ev,
+template <int N, int H, class LR, class T, class TIN>
+__device__ __forceinline__ void load_evol_sys(T (&x)[H], int roff, const TIN *ev,
                                               const LR &L, int role_m, int role_p,
                                               bool valid) {
     const int col = L.role == role_m ? L.rc
@@ -228,14 +268,14 @@ __device__ __forceinline__ void load_evol_sys(double (&x)[H], int roff, const do
                   : L.role == RHS    ? 2 * N : -1;
     const bool ld = valid && col >= 0;
 #pragma unroll
-    for (int r = 0; r < N; ++r) x[roff + r] = ld ? ev[r * (2 * N + 1) + col] : 0.0;
+    for (int r = 0; r < N; ++r) x[roff + r] = ld ? T(ev[r * (2 * N + 1) + col]) : T(0);
 }
 
 // Raw observation step j, rows [G_j | o_j] (m rows, zero rows up to MM), and
 // the covariance data for its whitening: cv = column (gl - cl0) of C_j on the
 // lanes cl0 .. cl0+MM-1 (identity columns for padding rows), or the variances.
-template <int N, int MM, int H, class LR>
-__device__ __forceinline__ void load_obs_raw(double (&x)[H], int roff, double (&cv)[MM],
+template <int N, int MM, int H, class LR, class T>
+__device__ __forceinline__ void load_obs_raw(T (&x)[H], int roff, T (&cv)[MM],
                                              int64_t j, const LR &L, int gl, int own,
                                              int cl0, const FwdArgs &a, bool valid,
                                              int rhs = RHS) {
@@ -246,25 +286,25 @@ __device__ __forceinline__ void load_obs_raw(double (&x)[H], int roff, double (&
     const double *oj = a.o + j * (int64_t)m;
 #pragma unroll
     for (int r = 0; r < MM; ++r)
-        x[roff + r] = (ld && r < m) ? (col < N ? Gj[r * N + col] : oj[r]) : 0.0;
+        x[roff + r] = (ld && r < m) ? T(col < N ? Gj[r * N + col] : oj[r]) : T(0);
     if (a.C_diag) {
         const double *Cj = a.C + j * (int64_t)m;
 #pragma unroll
-        for (int r = 0; r < MM; ++r) cv[r] = (valid && r < m) ? Cj[r] : 1.0;
+        for (int r = 0; r < MM; ++r) cv[r] = (valid && r < m) ? T(Cj[r]) : T(1);
     } else {
         const double *Cj = a.C + j * (int64_t)m * m;
         const int q = gl - cl0;
         const bool mine = (unsigned)q < (unsigned)MM;
 #pragma unroll
         for (int r = 0; r < MM; ++r)
-            cv[r] = !mine ? 0.0 : (valid && q < m && r < m) ? Cj[r * m + q] : (r == q ? 1.0 : 0.0);
+            cv[r] = !mine ? T(0) : (valid && q < m && r < m) ? T(Cj[r * m + q]) : T(r == q ? 1 : 0);
     }
 }
 
 // Raw evolution step i (1..k), rows [-F_i | H_i | c_i] (zero block when
 // !valid), with its covariance data as in load_obs_raw.
-template <int N, int H, class LR>
-__device__ __forceinline__ void load_evol_raw(double (&x)[H], int roff, double (&cv)[N], int64_t i,
+template <int N, int H, class LR, class T>
+__device__ __forceinline__ void load_evol_raw(T (&x)[H], int roff, T (&cv)[N], int64_t i,
                                               const LR &L, int gl, int role_m,
                                               int role_p, int cl0, const FwdArgs &a, bool valid) {
     const int64_t t = i - 1;  // ABI entry of step i
@@ -279,41 +319,41 @@ __device__ __forceinline__ void load_evol_raw(double (&x)[H], int roff, double (
             else if (L.role == role_p) v = Hm ? Hm[r * N + L.rc] : (r == L.rc ? 1.0 : 0.0);
             else if (L.role == RHS) v = c[r];
         }
-        x[roff + r] = v;
+        x[roff + r] = T(v);
     }
     if (a.K_diag) {
         const double *Kt = a.K + t * N;
 #pragma unroll
-        for (int r = 0; r < N; ++r) cv[r] = valid ? Kt[r] : 1.0;
+        for (int r = 0; r < N; ++r) cv[r] = valid ? T(Kt[r]) : T(1);
     } else {
         const double *Kt = a.K + t * N * N;
         const int q = gl - cl0;
         const bool mine = (unsigned)q < (unsigned)N;
 #pragma unroll
         for (int r = 0; r < N; ++r)
-            cv[r] = !mine ? 0.0 : valid ? Kt[r * N + q] : (r == q ? 1.0 : 0.0);
+            cv[r] = !mine ? T(0) : valid ? T(Kt[r * N + q]) : T(r == q ? 1 : 0);
     }
 }
 
-template <int H, int D>
-__device__ __forceinline__ void whiten(bool diag, double (&x)[H], int roff, double (&cv)[D],
+template <int H, int D, class T>
+__device__ __forceinline__ void whiten(bool diag, T (&x)[H], int roff, T (&cv)[D],
                                        int gl, int gbase, int cl0, bool &bad) {
     if (diag)
-        whiten_diag<H, D>(x, roff, cv, gl, bad);
+        whiten_diag<H, D, T>(x, roff, cv, gl, bad);
     else
-        whiten_dense<H, D>(x, roff, cv, gl, gbase, cl0, bad);
+        whiten_dense<H, D, T>(x, roff, cv, gl, gbase, cl0, bad);
 }
 
 // ------------------------------------------------------ shared epilogues
 
-template <int N, int H, class LR>
-__device__ __forceinline__ void diag_stats(const double (&x)[H], const LR &L, bool valid,
+template <int N, int H, class LR, class T>
+__device__ __forceinline__ void diag_stats(const T (&x)[H], const LR &L, bool valid,
                                            double &dmin, double &dmax, bool &nonfinite) {
     if (!valid || L.role != CUR) return;
     double d = 0.0;
 #pragma unroll
     for (int r = 0; r < N; ++r)
-        if (L.rc == r) d = fabs(x[r]);
+        if (L.rc == r) d = fabs(double(x[r]));
     if (!isfinite(d)) nonfinite = true;
     dmin = fmin(dmin, d);
     dmax = fmax(dmax, d);
@@ -349,11 +389,22 @@ __device__ __forceinline__ void block_minmax(double &dmin, double &dmax, bool ba
 }
 
 // R-row record: n rows of [R_jj | R_j,right | rho | R_j,left] = lanes 0..3n
-template <int N, int H>
-__device__ __forceinline__ void store_rrow(double *rec, const double (&x)[H], int gl, bool valid) {
+template <int N, int H, class T>
+__device__ __forceinline__ void store_rrow(T *rec, const T (&x)[H], int gl, bool valid) {
     if (!valid || gl > 3 * N) return;
 #pragma unroll
     for (int r = 0; r < N; ++r) rec[r * (3 * N + 1) + gl] = x[r];
+}
+
+// Record idx of a segment whose records are `stride` doubles apart; records of
+// FP32 levels hold floats in the first half of their slot.
+template <class T>
+__device__ __forceinline__ T *slot(double *base, int64_t idx, int stride) {
+    return reinterpret_cast<T *>(base + idx * stride);
+}
+template <class T>
+__device__ __forceinline__ const T *slot(const double *base, int64_t idx, int stride) {
+    return reinterpret_cast<const T *>(base + idx * stride);
 }
 
 // ------------------------------------------------------------- forward level
@@ -361,42 +412,43 @@ __device__ __forceinline__ void store_rrow(double *rec, const double (&x)[H], in
 // The last column jl = N_l - 1 of a level with N_l odd (even, no right
 // neighbour): its R row (record t+1), and its Z rows, which touch only column
 // jl - 1, stacked under the step-3 triangle Onew of the last unit t.
-template <int N, int MM, bool RAW>
+template <int N, int MM, bool RAW, class T, class TIN>
 __device__ __forceinline__ void fold_part(const FwdArgs &a, int64_t t, int gl, int gb,
-                                          const LaneRole<N> &L, double (&Onew)[N], double &dmin,
+                                          const LaneRole<N> &L, T (&Onew)[N], double &dmin,
                                           double &dmax, bool &bad, bool &nonfinite) {
     using GE = Geo<N>;
     constexpr int RO = RAW ? MM : N;
     constexpr int HC = 2 * N;
     // the last column jl = N_l - 1 (even, no right neighbour)
     const int64_t jl = a.Nl - 1;
-    double A2[RO], C2[HC];
+    T A2[RO], C2[HC];
 #pragma unroll
-    for (int r = N; r < HC; ++r) C2[r] = 0.0;
+    for (int r = N; r < HC; ++r) C2[r] = T(0);
     if constexpr (RAW) {
-        double cvO[MM], cvE[N];
+        T cvO[MM], cvE[N];
         load_obs_raw<N, MM>(A2, 0, cvO, jl, L, gl, CUR, 0, a, true);
         load_evol_raw<N>(C2, 0, cvE, jl, L, gl, LEFT, CUR, 2 * N + 1, a, true);
         whiten<RO, MM>(a.C_diag, A2, 0, cvO, gl, gb, 0, bad);
         whiten<HC, N>(a.K_diag, C2, 0, cvE, gl, gb, 2 * N + 1, bad);
     } else {
-        load_obs_sys<N>(A2, 0, a.sys_in + jl * GE::SREC, L, CUR, true);
-        load_evol_sys<N>(C2, 0, a.sys_in + jl * GE::SREC + GE::OREC, L, LEFT, CUR, true);
+        const TIN *rec = slot<TIN>(a.sys_in, jl, GE::SREC);
+        load_obs_sys<N>(A2, 0, rec, L, CUR, true);
+        load_evol_sys<N>(C2, 0, rec + GE::OREC, L, LEFT, CUR, true);
     }
     hqr<RO, N>(A2, gl, gb, 0);
 #pragma unroll
-    for (int r = 0; r < N; ++r) C2[N + r] = r < RO ? A2[r] : 0.0;
+    for (int r = 0; r < N; ++r) C2[N + r] = r < RO ? A2[r] : T(0);
     hqr<HC, N>(C2, gl, gb, 0);
-    store_rrow<N>(a.rrows + (t + 1) * GE::RREC, C2, gl, true);
+    store_rrow<N>(slot<T>(a.rrows, t + 1, GE::RREC), C2, gl, true);
     diag_stats<N>(C2, L, true, dmin, dmax, nonfinite);
     // Z rows (left lanes) move onto the right lanes; rhs keeps zeta
     const int src = gb + ((L.role == RIGHT) ? gl + N + 1 : gl);
-    double B2[2 * N];
+    T B2[2 * N];
 #pragma unroll
     for (int r = 0; r < N; ++r) {
-        const double z = bperm(C2[N + r], src);
+        const T z = bperm(C2[N + r], src);
         B2[r] = Onew[r];
-        B2[N + r] = (L.role == RIGHT || L.role == RHS) ? z : 0.0;
+        B2[N + r] = (L.role == RIGHT || L.role == RHS) ? z : T(0);
     }
     hqr<2 * N, N>(B2, gl, gb, N);
 #pragma unroll
@@ -406,7 +458,7 @@ __device__ __forceinline__ void fold_part(const FwdArgs &a, int64_t t, int gl, i
 // One unit of a forward level: even column j = 2t and its right neighbour
 // (plus, with INLINE_FOLD, the last column when it is the folding unit; the
 // per-level kernels leave that to k_fold).  No workgroup barrier.
-template <int N, int MM, bool RAW, bool INLINE_FOLD>
+template <int N, int MM, bool RAW, bool INLINE_FOLD, class T, class TIN>
 __device__ __forceinline__ void fwd_unit(const FwdArgs &a, int64_t t, bool in, int gl, int gb,
                                          double &dmin, double &dmax, bool &bad, bool &nonfinite) {
     using GE = Geo<N>;
@@ -421,11 +473,11 @@ __device__ __forceinline__ void fwd_unit(const FwdArgs &a, int64_t t, bool in, i
     // A = [O_j | 0 | w_j ; E-_{j+1} | E+_{j+1} | eta_{j+1}]      (cur, right, rhs lanes)
     // B = [D~_{j+1} | gamma ; O_{j+1} | w_{j+1}]                  (right, rhs lanes)
     // C = [E+_j | 0 | eta_j | E-_j ; R~_j | X_j | rho~_j | 0]     (cur, right, rhs, left lanes)
-    double A[HA], B[HB], C[HC];
+    T A[HA], B[HB], C[HC];
 #pragma unroll
-    for (int r = N; r < HC; ++r) C[r] = 0.0;
+    for (int r = N; r < HC; ++r) C[r] = T(0);
     if constexpr (RAW) {
-        double cvOa[MM], cvOb[MM], cvEa[N], cvEc[N];
+        T cvOa[MM], cvOb[MM], cvEa[N], cvEc[N];
         load_obs_raw<N, MM>(A, 0, cvOa, j, L, gl, CUR, 0, a, valid);
         load_evol_raw<N>(A, RO, cvEa, j + 1, L, gl, CUR, RIGHT, 0, a, valid);
         load_obs_raw<N, MM>(B, RO, cvOb, j + 1, L, gl, RIGHT, N, a, valid);
@@ -435,10 +487,11 @@ __device__ __forceinline__ void fwd_unit(const FwdArgs &a, int64_t t, bool in, i
         whiten<HB, MM>(a.C_diag, B, RO, cvOb, gl, gb, N, bad);
         whiten<HC, N>(a.K_diag, C, 0, cvEc, gl, gb, 2 * N + 1, bad);
     } else {
-        const double *rec = a.sys_in + j * GE::SREC;
+        const TIN *rec = slot<TIN>(a.sys_in, j, GE::SREC);
         load_obs_sys<N>(A, 0, rec, L, CUR, valid);
-        load_evol_sys<N>(A, RO, rec + GE::SREC + GE::OREC, L, CUR, RIGHT, valid);
-        load_obs_sys<N>(B, RO, rec + GE::SREC, L, RIGHT, valid);
+        const TIN *rec1 = slot<TIN>(a.sys_in, j + 1, GE::SREC);
+        load_evol_sys<N>(A, RO, rec1 + GE::OREC, L, CUR, RIGHT, valid);
+        load_obs_sys<N>(B, RO, rec1, L, RIGHT, valid);
         load_evol_sys<N>(C, 0, rec + GE::OREC, L, LEFT, CUR, valid && j >= 1);
     }
 
@@ -453,7 +506,7 @@ __device__ __forceinline__ void fwd_unit(const FwdArgs &a, int64_t t, bool in, i
     hqr<HB, N>(B, gl, gb, N);
     hqr<HC, N>(C, gl, gb, 0);
 
-    store_rrow<N>(a.rrows + t * GE::RREC, C, gl, valid);
+    store_rrow<N>(slot<T>(a.rrows, t, GE::RREC), C, gl, valid);
     diag_stats<N>(C, L, valid, dmin, dmax, nonfinite);
     // reduced column t, evolution block (Z_j | X~_j | zeta_j) from the bottom of step 2
     if (valid) {
@@ -461,22 +514,22 @@ __device__ __forceinline__ void fwd_unit(const FwdArgs &a, int64_t t, bool in, i
                      : L.role == RIGHT ? N + L.rc
                      : L.role == RHS ? 2 * N : -1;
         if (ec >= 0) {
-            double *rec = a.sys_out + t * GE::SREC + GE::OREC;
+            T *rec = slot<T>(a.sys_out, t, GE::SREC) + GE::OREC;
 #pragma unroll
             for (int r = 0; r < N; ++r) rec[r * (2 * N + 1) + ec] = C[N + r];
         }
     }
-    double Onew[N];
+    T Onew[N];
 #pragma unroll
-    for (int r = 0; r < N; ++r) Onew[r] = r < PB ? B[r] : 0.0;
+    for (int r = 0; r < N; ++r) Onew[r] = r < PB ? B[r] : T(0);
 
-    if (INLINE_FOLD && fold) fold_part<N, MM, RAW>(a, t, gl, gb, L, Onew, dmin, dmax, bad, nonfinite);
+    if (INLINE_FOLD && fold) fold_part<N, MM, RAW, T, TIN>(a, t, gl, gb, L, Onew, dmin, dmax, bad, nonfinite);
 
     // reduced column t, observation block from step 3 (with the fold, if any)
     if (valid) {
         const int oc = L.role == RIGHT ? L.rc : (L.role == RHS ? N : -1);
         if (oc >= 0) {
-            double *rec = a.sys_out + t * GE::SREC;
+            T *rec = slot<T>(a.sys_out, t, GE::SREC);
 #pragma unroll
             for (int r = 0; r < N; ++r) rec[r * (N + 1) + oc] = Onew[r];
         }
@@ -485,7 +538,7 @@ __device__ __forceinline__ void fwd_unit(const FwdArgs &a, int64_t t, bool in, i
 
 // Base case: a level with a single column; R = triangular factor of its
 // observation block (Section III, recursion end; Algorithm 2, one column).
-template <int N, int MM, bool RAW>
+template <int N, int MM, bool RAW, class TIN>
 __device__ __forceinline__ void base_unit(const FwdArgs &a, bool valid, int gl, int gb,
                                           double &dmin, double &dmax, bool &bad, bool &nonfinite) {
     constexpr int RO = RAW ? MM : N;
@@ -496,7 +549,7 @@ __device__ __forceinline__ void base_unit(const FwdArgs &a, bool valid, int gl, 
         load_obs_raw<N, MM>(A, 0, cv, 0, L, gl, CUR, 0, a, valid);
         whiten<RO, MM>(a.C_diag, A, 0, cv, gl, gb, 0, bad);
     } else {
-        load_obs_sys<N>(A, 0, a.sys_in, L, CUR, valid);
+        load_obs_sys<N>(A, 0, slot<TIN>(a.sys_in, 0, Geo<N>::SREC), L, CUR, valid);
     }
     hqr<RO, N>(A, gl, gb, 0);
     double R[N];
@@ -526,19 +579,19 @@ __device__ __forceinline__ void reduce_slots(const double *slots, int64_t nprev,
     }
 }
 
-__device__ __forceinline__ void rank_flag(double dmin, double dmax, unsigned *flags) {
-    if (threadIdx.x == 0 && !(dmin > 64.0 * 2.220446049250313e-16 * dmax))
+__device__ __forceinline__ void rank_flag(double dmin, double dmax, double tol, unsigned *flags) {
+    if (threadIdx.x == 0 && !(dmin > tol * dmax))
         atomicOr(flags, FLAG_RANK);
 }
 
 // one forward level, one unit per G lanes, many workgroups
-template <int N, int MM, bool RAW>
+template <int N, int MM, bool RAW, class T, class TIN>
 __global__ __launch_bounds__(kBlock) void k_forward(FwdArgs a) {
     const Grp<N> g;
     bool bad = false, nonfinite = false;
     double dmin = INFINITY, dmax = 0.0;
     const int64_t t = (int64_t)blockIdx.x * Geo<N>::UPB + g.ui;
-    fwd_unit<N, MM, RAW, false>(a, t, g.in, g.gl, g.gbase, dmin, dmax, bad, nonfinite);
+    fwd_unit<N, MM, RAW, false, T, TIN>(a, t, g.in, g.gl, g.gbase, dmin, dmax, bad, nonfinite);
     block_minmax<kBlock>(dmin, dmax, bad, nonfinite, a.flags);
     if (threadIdx.x == 0) {
         a.slots[2 * blockIdx.x] = dmin;
@@ -549,7 +602,7 @@ __global__ __launch_bounds__(kBlock) void k_forward(FwdArgs a) {
 // The fold of a level with N_l odd, after that level's k_forward: one unit
 // reloads the last unit's step-3 triangle, eliminates the last column and
 // re-triangularizes.  Writes one slot (a.fold_slot).
-template <int N, int MM, bool RAW>
+template <int N, int MM, bool RAW, class T, class TIN>
 __global__ __launch_bounds__(kBlock) void k_fold(FwdArgs a) {
     using GE = Geo<N>;
     const Grp<N> g;
@@ -559,13 +612,13 @@ __global__ __launch_bounds__(kBlock) void k_fold(FwdArgs a) {
     double dmin = INFINITY, dmax = 0.0;
     const int64_t t = a.units - 1;
     if (g.ui == 0) {  // one unit: lanes of the other units stay idle
-        double Onew[N];
-        load_obs_sys<N>(Onew, 0, a.sys_out + t * GE::SREC, L, RIGHT, valid);
-        fold_part<N, MM, RAW>(a, t, g.gl, g.gbase, L, Onew, dmin, dmax, bad, nonfinite);
+        T Onew[N];
+        load_obs_sys<N>(Onew, 0, slot<T>(a.sys_out, t, GE::SREC), L, RIGHT, valid);
+        fold_part<N, MM, RAW, T, TIN>(a, t, g.gl, g.gbase, L, Onew, dmin, dmax, bad, nonfinite);
         if (valid) {
             const int oc = L.role == RIGHT ? L.rc : (L.role == RHS ? N : -1);
             if (oc >= 0) {
-                double *rec = a.sys_out + t * GE::SREC;
+                T *rec = slot<T>(a.sys_out, t, GE::SREC);
 #pragma unroll
                 for (int r = 0; r < N; ++r) rec[r * (N + 1) + oc] = Onew[r];
             }
@@ -599,15 +652,15 @@ __global__ __launch_bounds__(kTailBlock) void k_fwd_tail(FwdTailArgs ta) {
         a.rrows = ta.rrows + ta.rec_off[l] * GE::RREC;
         if (a.Nl == 1) {
             if (RAW0 && l == 0)
-                base_unit<N, MM, true>(a, g.in && g.ui == 0, g.gl, g.gbase, dmin, dmax, bad, nonfinite);
+                base_unit<N, MM, true, double>(a, g.in && g.ui == 0, g.gl, g.gbase, dmin, dmax, bad, nonfinite);
             else
-                base_unit<N, MM, false>(a, g.in && g.ui == 0, g.gl, g.gbase, dmin, dmax, bad, nonfinite);
+                base_unit<N, MM, false, double>(a, g.in && g.ui == 0, g.gl, g.gbase, dmin, dmax, bad, nonfinite);
         } else {
             for (int64_t t0 = 0; t0 < a.units; t0 += UPB) {
                 if (RAW0 && l == 0)
-                    fwd_unit<N, MM, true, true>(a, t0 + g.ui, g.in, g.gl, g.gbase, dmin, dmax, bad, nonfinite);
+                    fwd_unit<N, MM, true, true, double, double>(a, t0 + g.ui, g.in, g.gl, g.gbase, dmin, dmax, bad, nonfinite);
                 else
-                    fwd_unit<N, MM, false, true>(a, t0 + g.ui, g.in, g.gl, g.gbase, dmin, dmax, bad, nonfinite);
+                    fwd_unit<N, MM, false, true, double, double>(a, t0 + g.ui, g.in, g.gl, g.gbase, dmin, dmax, bad, nonfinite);
             }
         }
         __threadfence();
@@ -615,7 +668,7 @@ __global__ __launch_bounds__(kTailBlock) void k_fwd_tail(FwdTailArgs ta) {
     }
     reduce_slots(ta.slots, ta.nprev, dmin, dmax);
     block_minmax<kTailBlock>(dmin, dmax, bad, nonfinite, ta.a.flags);
-    rank_flag(dmin, dmax, ta.a.flags);
+    rank_flag(dmin, dmax, ta.rank_tol, ta.a.flags);
 }
 
 // ------------------------------------------------------------ backward level
@@ -640,7 +693,7 @@ struct BwdSmem {
 // One block row of level l (record t): back-substitution and/or the SelInv
 // step of Algorithm 2.  Uses this unit's LDS region and workgroup barriers, so
 // every thread of the workgroup must call it the same number of times.
-template <int N, bool DO_Y, bool DO_COV>
+template <int N, bool DO_Y, bool DO_COV, class TR>
 __device__ __forceinline__ void bwd_unit(const BwdArgs &a, int l, int64_t t, int64_t units,
                                          bool store_s, bool in, int gl, double *Rr) {
     using GE = Geo<N>;
@@ -662,8 +715,8 @@ __device__ __forceinline__ void bwd_unit(const BwdArgs &a, int l, int64_t t, int
 
     // stage the record and the neighbour data (lanes outside a unit skip)
     if (in) {
-        const double *rec = a.rrows_all + (a.rec_off[l] + t) * GE::RREC;
-        for (int e = gl; e < SM::RR; e += G) Rr[e] = valid ? rec[e] : (e % (W + 1) == 0 ? 1.0 : 0.0);
+        const TR *rec = slot<TR>(a.rrows_all, a.rec_off[l] + t, GE::RREC);
+        for (int e = gl; e < SM::RR; e += G) Rr[e] = valid ? double(rec[e]) : (e % (W + 1) == 0 ? 1.0 : 0.0);
         if constexpr (DO_Y) {
             for (int e = gl; e < 2 * N; e += G) {
                 const bool left = e < N;
@@ -796,14 +849,14 @@ __device__ __forceinline__ void bwd_unit(const BwdArgs &a, int l, int64_t t, int
     __syncthreads();  // the LDS region is reused by the next call
 }
 
-template <int N, bool DO_Y, bool DO_COV>
+template <int N, bool DO_Y, bool DO_COV, class TR>
 __global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a) {
     using SM = BwdSmem<N, DO_Y, DO_COV>;
     __shared__ double smem[Geo<N>::UPB * SM::PER];
     const Grp<N> g;
     const int l = a.level;
     const int64_t t = (int64_t)blockIdx.x * Geo<N>::UPB + g.ui;
-    bwd_unit<N, DO_Y, DO_COV>(a, l, t, (a.Nl[l] + 1) / 2, a.store_s && l >= 1, g.in, g.gl,
+    bwd_unit<N, DO_Y, DO_COV, TR>(a, l, t, (a.Nl[l] + 1) / 2, a.store_s && l >= 1, g.in, g.gl,
                               smem + g.ui * SM::PER);
 }
 
@@ -817,7 +870,7 @@ __global__ __launch_bounds__(TB) void k_bwd_tail(BwdArgs a) {
     for (int l = a.level; l >= a.l_lo; --l) {
         const int64_t units = (a.Nl[l] + 1) / 2;
         for (int64_t t0 = 0; t0 < units; t0 += UPB)
-            bwd_unit<N, DO_Y, DO_COV>(a, l, t0 + g.ui, units, a.store_s && l >= 1, g.in, g.gl,
+            bwd_unit<N, DO_Y, DO_COV, double>(a, l, t0 + g.ui, units, a.store_s && l >= 1, g.in, g.gl,
                                       smem + g.ui * SM::PER);
         __threadfence();
         __syncthreads();
@@ -833,15 +886,15 @@ struct BwdTailBlock {
     static constexpr int TB = (8 * Geo<N>::UPW * PER * 8 <= 96 * 1024) ? 512 : kBlock;
 };
 
-template <int N, int MM, bool RAW>
+template <int N, int MM, bool RAW, class T, class TIN>
 static void launch_fwd_t(const FwdArgs &a, hipStream_t s) {
     const int64_t blocks = (a.units + Geo<N>::UPB - 1) / Geo<N>::UPB;
-    hipLaunchKernelGGL((k_forward<N, MM, RAW>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_forward<N, MM, RAW, T, TIN>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
 }
 
-template <int N, int MM, bool RAW>
+template <int N, int MM, bool RAW, class T, class TIN>
 static void launch_fold_t(const FwdArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((k_fold<N, MM, RAW>), dim3(1), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_fold<N, MM, RAW, T, TIN>), dim3(1), dim3(kBlock), 0, s, a);
 }
 
 template <int N, int MM, bool RAW0>
@@ -849,11 +902,11 @@ static void launch_fwd_tail_t(const FwdTailArgs &a, hipStream_t s) {
     hipLaunchKernelGGL((k_fwd_tail<N, MM, RAW0>), dim3(1), dim3(kTailBlock), 0, s, a);
 }
 
-template <int N, bool Y, bool COV>
+template <int N, bool Y, bool COV, class TR>
 static void launch_bwd_t(const BwdArgs &a, hipStream_t s) {
     const int64_t units = (a.Nl[a.level] + 1) / 2;
     const int64_t blocks = (units + Geo<N>::UPB - 1) / Geo<N>::UPB;
-    hipLaunchKernelGGL((k_backward<N, Y, COV>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_backward<N, Y, COV, TR>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
 }
 
 template <int N, bool Y, bool COV>
@@ -862,18 +915,23 @@ static void launch_bwd_tail_t(const BwdArgs &a, hipStream_t s) {
     hipLaunchKernelGGL((k_bwd_tail<N, Y, COV, TB>), dim3(1), dim3(TB), 0, s, a);
 }
 
+// variants: forward [FP64 | FP32 | FP64 from FP32 records (switch level)],
+// backward [mode][record type FP64 | FP32]
 template <int N, int MM>
 constexpr KernelSet make_set() {
     return KernelSet{N,
                      MM,
-                     &launch_fwd_t<N, MM, true>,
-                     &launch_fwd_t<N, MM, false>,
-                     &launch_fold_t<N, MM, true>,
-                     &launch_fold_t<N, MM, false>,
+                     {&launch_fwd_t<N, MM, true, double, double>, &launch_fwd_t<N, MM, true, float, double>},
+                     {&launch_fwd_t<N, MM, false, double, double>, &launch_fwd_t<N, MM, false, float, float>,
+                      &launch_fwd_t<N, MM, false, double, float>},
+                     {&launch_fold_t<N, MM, true, double, double>, &launch_fold_t<N, MM, true, float, double>},
+                     {&launch_fold_t<N, MM, false, double, double>, &launch_fold_t<N, MM, false, float, float>,
+                      &launch_fold_t<N, MM, false, double, float>},
                      &launch_fwd_tail_t<N, MM, true>,
                      &launch_fwd_tail_t<N, MM, false>,
-                     {&launch_bwd_t<N, true, false>, &launch_bwd_t<N, false, true>,
-                      &launch_bwd_t<N, true, true>},
+                     {{&launch_bwd_t<N, true, false, double>, &launch_bwd_t<N, true, false, float>},
+                      {&launch_bwd_t<N, false, true, double>, &launch_bwd_t<N, false, true, float>},
+                      {&launch_bwd_t<N, true, true, double>, &launch_bwd_t<N, true, true, float>}},
                      {&launch_bwd_tail_t<N, true, false>, &launch_bwd_tail_t<N, false, true>,
                       &launch_bwd_tail_t<N, true, true>},
                      Geo<N>::UPB,

@@ -52,36 +52,45 @@ struct BRole {
 // row needs a select.  `part` lanes apply the reflector, others leave their
 // column untouched.  The pivot diagonal ends as beta up to rounding; strictly
 // lower parts of pivot columns are set to zero at the end.
-template <int H, int HR, int NP>
-__device__ __forceinline__ void hqr_lds(double (&x)[H], int gl, int pl0, bool part, double *buf,
+template <int H, int HR, int NP, class T>
+__device__ __forceinline__ void hqr_lds(T (&x)[H], int gl, int pl0, bool part, T *buf,
                                         int &ph) {
     constexpr int P = NP < HR ? NP : HR;
     constexpr int CH = 8;
 #pragma unroll 1
     for (int p = 0; p < P; ++p) {
-        double *bp = buf + (ph & 1) * (H + 2);
+        T *bp = buf + (ph & 1) * (H + 2);
         ++ph;
         if (gl == pl0 + p) {
-            double alpha = 0.0, s0 = 0.0, s1 = 0.0;
+            T alpha = 0, am = 0;
 #pragma unroll
             for (int r = 0; r < HR; ++r) {
                 if (r == p) alpha = x[r];
-                const double m = r > p ? x[r] : 0.0;
+                if (r >= p) am = fmax(am, fabs(x[r]));
+            }
+            // sum of squares scaled by the largest entry in FP32, plain in FP64
+            const T sc = sizeof(T) == 4 ? (am > T(0) ? rcp_nr(am) : T(0)) : T(1);
+            if (sizeof(T) != 4) am = T(1);
+            T s0 = 0, s1 = 0;
+#pragma unroll
+            for (int r = 0; r < HR; ++r) {
+                const T m = r > p ? x[r] * sc : T(0);
                 if (r & 1) s0 = fma(m, m, s0);
                 else s1 = fma(m, m, s1);
             }
-            const double xn2 = s0 + s1;
-            const double s = fma(alpha, alpha, xn2);
-            const double nrm = sqrt(s);
-            const double beta = -copysign(nrm, alpha);
-            bp[H] = xn2 != 0.0 ? rcp_nr(fma(fabs(alpha), nrm, s)) : 0.0;
-            const double v0 = alpha - beta;
+            const T as = alpha * sc;
+            const T xn2 = s0 + s1;
+            const T s = fma(as, as, xn2);
+            const T nrs = sqrt(s);
+            const T beta = -copysign(nrs * am, alpha);
+            bp[H] = xn2 != T(0) ? sc * sc * rcp_nr(fma(fabs(as), nrs, s)) : T(0);
+            const T v0 = alpha - beta;
 #pragma unroll
-            for (int r = 0; r < HR; ++r) bp[r] = r < p ? 0.0 : (r == p ? v0 : x[r]);
+            for (int r = 0; r < HR; ++r) bp[r] = r < p ? T(0) : (r == p ? v0 : x[r]);
         }
         __syncthreads();
         if (part) {
-            double w0 = 0.0, w1 = 0.0;
+            T w0 = 0, w1 = 0;
 #pragma unroll
             for (int c0 = 0; c0 < HR; c0 += CH) {
                 if (c0 + CH > p) {
@@ -92,7 +101,7 @@ __device__ __forceinline__ void hqr_lds(double (&x)[H], int gl, int pl0, bool pa
                     }
                 }
             }
-            const double w = (w0 + w1) * bp[H];
+            const T w = (w0 + w1) * bp[H];
             __asm__ volatile("" ::: "memory");  // re-read the slot instead of holding it in VGPRs
 #pragma unroll
             for (int c0 = 0; c0 < HR; c0 += CH) {
@@ -106,40 +115,40 @@ __device__ __forceinline__ void hqr_lds(double (&x)[H], int gl, int pl0, bool pa
     const unsigned q = (unsigned)(gl - pl0);
 #pragma unroll
     for (int r = 1; r < HR; ++r)
-        if (q < (unsigned)(r < P ? r : P)) x[r] = 0.0;
+        if (q < (unsigned)(r < P ? r : P)) x[r] = T(0);
 }
 
 // dense whitening with the Cholesky column published through LDS (see
 // whiten_dense); buf holds two slots of H + 2 doubles (the same slots as
 // hqr_lds, so consecutive sweeps never write a slot another lane still reads)
-template <int H, int D>
-__device__ __forceinline__ void whiten_lds(double (&x)[H], int roff, double (&cv)[D], int gl,
-                                           int cl0, bool part, double *buf, int &ph, bool &bad) {
+template <int H, int D, class T>
+__device__ __forceinline__ void whiten_lds(T (&x)[H], int roff, T (&cv)[D], int gl,
+                                           int cl0, bool part, T *buf, int &ph, bool &bad) {
 #pragma unroll 1
     for (int p = 0; p < D; ++p) {
-        double *bp = buf + (ph & 1) * (H + 2);
+        T *bp = buf + (ph & 1) * (H + 2);
         ++ph;
         if (gl == cl0 + p) {
-            double piv = 0.0;
+            T piv = 0;
 #pragma unroll
             for (int r = 0; r < D; ++r)
                 if (r == p) piv = cv[r];
-            if (!(piv > 0.0 && isfinite(piv))) bad = true;
-            const double il = rsq_nr(piv);
+            if (!(piv > T(0) && isfinite(piv))) bad = true;
+            const T il = rsq_nr(piv);
             bp[0] = il;
 #pragma unroll
-            for (int r = 0; r < D; ++r) bp[1 + r] = r > p ? cv[r] * il : 0.0;
+            for (int r = 0; r < D; ++r) bp[1 + r] = r > p ? cv[r] * il : T(0);
         }
         __syncthreads();
-        const double ilb = bp[0];
-        double cp = 0.0, xq = 0.0;
+        const T ilb = bp[0];
+        T cp = 0, xq = 0;
 #pragma unroll
         for (int r = 0; r < D; ++r)
             if (r == p) {
                 cp = cv[r];
                 xq = x[roff + r];
             }
-        const double f = cp * ilb, xp = xq * ilb;
+        const T f = cp * ilb, xp = xq * ilb;
 #pragma unroll
         for (int r = 0; r < D; ++r) cv[r] = fma(-bp[1 + r], f, cv[r]);
         if (part) {
@@ -150,14 +159,14 @@ __device__ __forceinline__ void whiten_lds(double (&x)[H], int roff, double (&cv
     }
 }
 
-template <int H, int D>
-__device__ __forceinline__ void whiten_blk(bool diag, double (&x)[H], int roff, double (&cv)[D],
-                                           int gl, int cl0, bool part, double *buf, int &ph,
+template <int H, int D, class T>
+__device__ __forceinline__ void whiten_blk(bool diag, T (&x)[H], int roff, T (&cv)[D],
+                                           int gl, int cl0, bool part, T *buf, int &ph,
                                            bool &bad) {
     if (diag) {
-        if (part) whiten_diag<H, D>(x, roff, cv, gl, bad);
+        if (part) whiten_diag<H, D, T>(x, roff, cv, gl, bad);
     } else {
-        whiten_lds<H, D>(x, roff, cv, gl, cl0, part, buf, ph, bad);
+        whiten_lds<H, D, T>(x, roff, cv, gl, cl0, part, buf, ph, bad);
     }
 }
 
@@ -166,9 +175,9 @@ __device__ __forceinline__ void whiten_blk(bool diag, double (&x)[H], int roff, 
 // The last column of a level with N_l odd (see fold_part): the u_j lanes
 // eliminate it, its Z rows go to the step-3 lanes and are stacked under
 // Onew, the last unit's step-3 triangle.  Whole workgroup, uniform.
-template <int N, int MM, bool RAW>
-__device__ __forceinline__ void blk_fold_part(const FwdArgs &a, int64_t t, double *bufs,
-                                              double *exch, double (&Onew)[N], double &dmin,
+template <int N, int MM, bool RAW, class T, class TIN>
+__device__ __forceinline__ void blk_fold_part(const FwdArgs &a, int64_t t, T *bufs,
+                                              T *exch, T (&Onew)[N], double &dmin,
                                               double &dmax, bool &bad, bool &nonfinite) {
     using BG = BGeo<N>;
     constexpr int RO = RAW ? MM : N;
@@ -177,39 +186,39 @@ __device__ __forceinline__ void blk_fold_part(const FwdArgs &a, int64_t t, doubl
     const BRole<N> L(gl);
     const bool isB = L.role == BRIGHT || L.role == BRHS;
     const bool isAC = L.role <= LEFT;
-    double *bufAC = bufs, *bufB = bufs + 2 * (H + 2);
+    T *bufAC = bufs, *bufB = bufs + 2 * (H + 2);
     int ph = 0;
     const int64_t jl = a.Nl - 1;
-    double X2[H];
+    T X2[H];
 #pragma unroll
-    for (int r = 0; r < H; ++r) X2[r] = 0.0;
+    for (int r = 0; r < H; ++r) X2[r] = T(0);
     if constexpr (RAW) {
-        double cvO[MM];
+        T cvO[MM];
         if (isAC) load_obs_raw<N, MM>(X2, 0, cvO, jl, L, gl, CUR, 0, a, true);
         else {
 #pragma unroll
-            for (int r = 0; r < MM; ++r) cvO[r] = 0.0;
+            for (int r = 0; r < MM; ++r) cvO[r] = T(0);
         }
         whiten_blk<H, MM>(a.C_diag, X2, 0, cvO, gl, 0, isAC, bufAC, ph, bad);
     } else {
-        if (isAC) load_obs_sys<N>(X2, 0, a.sys_in + jl * BG::SREC, L, CUR, true);
+        if (isAC) load_obs_sys<N>(X2, 0, slot<TIN>(a.sys_in, jl, BG::SREC), L, CUR, true);
     }
     hqr_lds<H, RO, N>(X2, gl, 0, isAC, bufAC, ph);
     if (isAC) {
 #pragma unroll
-        for (int r = N - 1; r >= 0; --r) X2[N + r] = r < RO ? X2[r] : 0.0;
+        for (int r = N - 1; r >= 0; --r) X2[N + r] = r < RO ? X2[r] : T(0);
     }
     if constexpr (RAW) {
-        double cvE[N];
+        T cvE[N];
 #pragma unroll
-        for (int r = 0; r < N; ++r) cvE[r] = 0.0;
+        for (int r = 0; r < N; ++r) cvE[r] = T(0);
         if (isAC) load_evol_raw<N>(X2, 0, cvE, jl, L, gl, LEFT, CUR, 2 * N + 1, a, true);
         whiten_blk<H, N>(a.K_diag, X2, 0, cvE, gl, 2 * N + 1, isAC, bufAC, ph, bad);
     } else {
-        if (isAC) load_evol_sys<N>(X2, 0, a.sys_in + jl * BG::SREC + BG::OREC, L, LEFT, CUR, true);
+        if (isAC) load_evol_sys<N>(X2, 0, slot<TIN>(a.sys_in, jl, BG::SREC) + BG::OREC, L, LEFT, CUR, true);
     }
     hqr_lds<H, H, N>(X2, gl, 0, isAC, bufAC, ph);
-    store_rrow<N>(a.rrows + (t + 1) * BG::RREC, X2, gl, true);
+    store_rrow<N>(slot<T>(a.rrows, t + 1, BG::RREC), X2, gl, true);
     diag_stats<N>(X2, L, true, dmin, dmax, nonfinite);
     // Z rows (u_{j-1} lanes) and zeta -> the step-3 lanes, stacked under O'
     if (L.role == LEFT || L.role == RHS) {
@@ -218,11 +227,11 @@ __device__ __forceinline__ void blk_fold_part(const FwdArgs &a, int64_t t, doubl
         for (int r = 0; r < N; ++r) exch[r * (N + 1) + col] = X2[N + r];
     }
     __syncthreads();
-    double X3[H];
+    T X3[H];
 #pragma unroll
     for (int r = 0; r < N; ++r) {
         X3[r] = Onew[r];
-        X3[N + r] = 0.0;
+        X3[N + r] = T(0);
     }
     if (isB) {
         const int col = L.role == BRIGHT ? L.rc : N;
@@ -234,9 +243,9 @@ __device__ __forceinline__ void blk_fold_part(const FwdArgs &a, int64_t t, doubl
     for (int r = 0; r < N; ++r) Onew[r] = X3[r];
 }
 
-template <int N, int MM, bool RAW, bool INLINE_FOLD>
-__device__ __forceinline__ void blk_fwd_unit(const FwdArgs &a, int64_t t, double *bufs,
-                                             double *exch, double &dmin, double &dmax, bool &bad,
+template <int N, int MM, bool RAW, bool INLINE_FOLD, class T, class TIN>
+__device__ __forceinline__ void blk_fwd_unit(const FwdArgs &a, int64_t t, T *bufs,
+                                             T *exch, double &dmin, double &dmax, bool &bad,
                                              bool &nonfinite) {
     using BG = BGeo<N>;
     constexpr int RO = RAW ? MM : N;
@@ -248,19 +257,19 @@ __device__ __forceinline__ void blk_fwd_unit(const FwdArgs &a, int64_t t, double
     const BRole<N> L(gl);
     const bool isB = L.role == BRIGHT || L.role == BRHS;
     const bool isAC = L.role <= LEFT;
-    double *bufAC = bufs, *bufB = bufs + 2 * (H + 2);
+    T *bufAC = bufs, *bufB = bufs + 2 * (H + 2);
     int ph = 0;
     const bool valid = t < a.units;
     const int64_t j = 2 * t;
     const bool fold = (a.Nl & 1) && t == a.units - 1;  // uniform over the workgroup
 
-    double X[H];
+    T X[H];
 #pragma unroll
-    for (int r = 0; r < H; ++r) X[r] = 0.0;
+    for (int r = 0; r < H; ++r) X[r] = T(0);
     if constexpr (RAW) {
-        double cvO[MM], cvE[N];
+        T cvO[MM], cvE[N];
 #pragma unroll
-        for (int r = 0; r < N; ++r) cvE[r] = 0.0;
+        for (int r = 0; r < N; ++r) cvE[r] = T(0);
         if (isB) {
             load_obs_raw<N, MM>(X, 0, cvO, j + 1, L, gl, BRIGHT, BG::BOFF, a, valid, BRHS);
         } else {
@@ -271,11 +280,10 @@ __device__ __forceinline__ void blk_fwd_unit(const FwdArgs &a, int64_t t, double
         whiten_blk<H, N>(a.K_diag, X, RO, cvE, gl, 0, isAC, bufAC, ph, bad);
     } else {
         if (isB) {
-            load_obs_sys<N>(X, 0, a.sys_in + (j + 1) * BG::SREC, L, BRIGHT, valid, BRHS);
+            load_obs_sys<N>(X, 0, slot<TIN>(a.sys_in, j + 1, BG::SREC), L, BRIGHT, valid, BRHS);
         } else {
-            const double *rec = a.sys_in + j * BG::SREC;
-            load_obs_sys<N>(X, 0, rec, L, CUR, valid);
-            load_evol_sys<N>(X, RO, rec + BG::SREC + BG::OREC, L, CUR, RIGHT, valid);
+            load_obs_sys<N>(X, 0, slot<TIN>(a.sys_in, j, BG::SREC), L, CUR, valid);
+            load_evol_sys<N>(X, RO, slot<TIN>(a.sys_in, j + 1, BG::SREC) + BG::OREC, L, CUR, RIGHT, valid);
         }
     }
 
@@ -293,15 +301,15 @@ __device__ __forceinline__ void blk_fwd_unit(const FwdArgs &a, int64_t t, double
         for (int r = N - 1; r >= 0; --r) X[N + r] = X[r];
     }
     if constexpr (RAW) {
-        double cvE[N];
+        T cvE[N];
 #pragma unroll
-        for (int r = 0; r < N; ++r) cvE[r] = 0.0;
+        for (int r = 0; r < N; ++r) cvE[r] = T(0);
         if (isAC) {
             load_evol_raw<N>(X, 0, cvE, j, L, gl, LEFT, CUR, 2 * N + 1, a, valid && j >= 1);
         }
         whiten_blk<H, N>(a.K_diag, X, 0, cvE, gl, 2 * N + 1, isAC, bufAC, ph, bad);
     } else {
-        if (isAC) load_evol_sys<N>(X, 0, a.sys_in + j * BG::SREC + BG::OREC, L, LEFT, CUR, valid && j >= 1);
+        if (isAC) load_evol_sys<N>(X, 0, slot<TIN>(a.sys_in, j, BG::SREC) + BG::OREC, L, LEFT, CUR, valid && j >= 1);
     }
     __syncthreads();
     if (isB) {
@@ -313,43 +321,43 @@ __device__ __forceinline__ void blk_fwd_unit(const FwdArgs &a, int64_t t, double
     // steps 2 (pivots u_j lanes) and 3 (pivots step-3 lanes) in one sweep
     hqr_lds<H, H, N>(X, gl, isB ? BG::BOFF : 0, isAC || isB, isB ? bufB : bufAC, ph);
 
-    store_rrow<N>(a.rrows + t * BG::RREC, X, gl, valid);
+    store_rrow<N>(slot<T>(a.rrows, t, BG::RREC), X, gl, valid);
     diag_stats<N>(X, L, valid, dmin, dmax, nonfinite);
     if (valid) {
         const int ec = L.role == LEFT ? L.rc
                      : L.role == RIGHT ? N + L.rc
                      : L.role == RHS ? 2 * N : -1;
         if (ec >= 0) {
-            double *rec = a.sys_out + t * BG::SREC + BG::OREC;
+            T *rec = slot<T>(a.sys_out, t, BG::SREC) + BG::OREC;
 #pragma unroll
             for (int r = 0; r < N; ++r) rec[r * (2 * N + 1) + ec] = X[N + r];
         }
     }
-    double Onew[N];
+    T Onew[N];
 #pragma unroll
-    for (int r = 0; r < N; ++r) Onew[r] = (isB && r < PB) ? X[r] : 0.0;
+    for (int r = 0; r < N; ++r) Onew[r] = (isB && r < PB) ? X[r] : T(0);
 
     if (INLINE_FOLD && fold && valid) {
         __syncthreads();
-        blk_fold_part<N, MM, RAW>(a, t, bufs, exch, Onew, dmin, dmax, bad, nonfinite);
+        blk_fold_part<N, MM, RAW, T, TIN>(a, t, bufs, exch, Onew, dmin, dmax, bad, nonfinite);
     }
 
     if (valid && isB) {
         const int oc = L.role == BRIGHT ? L.rc : N;
-        double *rec = a.sys_out + t * BG::SREC;
+        T *rec = slot<T>(a.sys_out, t, BG::SREC);
 #pragma unroll
         for (int r = 0; r < N; ++r) rec[r * (N + 1) + oc] = Onew[r];
     }
 }
 
-template <int N, int MM, bool RAW>
+template <int N, int MM, bool RAW, class T, class TIN>
 __global__ __launch_bounds__(BGeo<N>::TB) void k_blk_forward(FwdArgs a) {
     constexpr int H = 2 * N;
-    __shared__ double bufs[4 * (H + 2)];
-    __shared__ double exch[N * (N + 1)];
+    __shared__ T bufs[4 * (H + 2)];
+    __shared__ T exch[N * (N + 1)];
     bool bad = false, nonfinite = false;
     double dmin = INFINITY, dmax = 0.0;
-    blk_fwd_unit<N, MM, RAW, false>(a, blockIdx.x, bufs, exch, dmin, dmax, bad, nonfinite);
+    blk_fwd_unit<N, MM, RAW, false, T, TIN>(a, blockIdx.x, bufs, exch, dmin, dmax, bad, nonfinite);
     block_minmax<BGeo<N>::TB>(dmin, dmax, bad, nonfinite, a.flags);
     if (threadIdx.x == 0) {
         a.slots[2 * blockIdx.x] = dmin;
@@ -358,22 +366,22 @@ __global__ __launch_bounds__(BGeo<N>::TB) void k_blk_forward(FwdArgs a) {
 }
 
 // the fold of an odd level after its k_blk_forward (one workgroup)
-template <int N, int MM, bool RAW>
+template <int N, int MM, bool RAW, class T, class TIN>
 __global__ __launch_bounds__(BGeo<N>::TB) void k_blk_fold(FwdArgs a) {
     using BG = BGeo<N>;
     constexpr int H = 2 * N;
-    __shared__ double bufs[4 * (H + 2)];
-    __shared__ double exch[N * (N + 1)];
+    __shared__ T bufs[4 * (H + 2)];
+    __shared__ T exch[N * (N + 1)];
     const BRole<N> L(threadIdx.x);
     bool bad = false, nonfinite = false;
     double dmin = INFINITY, dmax = 0.0;
     const int64_t t = a.units - 1;
-    double Onew[N];
-    load_obs_sys<N>(Onew, 0, a.sys_out + t * BG::SREC, L, BRIGHT, true, BRHS);
-    blk_fold_part<N, MM, RAW>(a, t, bufs, exch, Onew, dmin, dmax, bad, nonfinite);
+    T Onew[N];
+    load_obs_sys<N>(Onew, 0, slot<T>(a.sys_out, t, BG::SREC), L, BRIGHT, true, BRHS);
+    blk_fold_part<N, MM, RAW, T, TIN>(a, t, bufs, exch, Onew, dmin, dmax, bad, nonfinite);
     if (L.role == BRIGHT || L.role == BRHS) {
         const int oc = L.role == BRIGHT ? L.rc : N;
-        double *rec = a.sys_out + t * BG::SREC;
+        T *rec = slot<T>(a.sys_out, t, BG::SREC);
 #pragma unroll
         for (int r = 0; r < N; ++r) rec[r * (N + 1) + oc] = Onew[r];
     }
@@ -421,7 +429,7 @@ __global__ __launch_bounds__(BGeo<N>::TB) void k_blk_fwd_tail(FwdTailArgs ta) {
                 whiten_blk<H, MM>(a.C_diag, X, 0, cv, gl, 0, isAC, bufs, ph, bad);
                 hqr_lds<H, RO0, N>(X, gl, 0, isAC, bufs, ph);
             } else {
-                if (isAC) load_obs_sys<N>(X, 0, a.sys_in, L, CUR, true);
+                if (isAC) load_obs_sys<N>(X, 0, slot<double>(a.sys_in, 0, BG::SREC), L, CUR, true);
                 hqr_lds<H, N, N>(X, gl, 0, isAC, bufs, ph);
             }
             const int rows = (RAW0 && l == 0) ? RO0 : N;
@@ -433,9 +441,9 @@ __global__ __launch_bounds__(BGeo<N>::TB) void k_blk_fwd_tail(FwdTailArgs ta) {
         } else {
             for (int64_t t = 0; t < a.units; ++t) {
                 if (RAW0 && l == 0)
-                    blk_fwd_unit<N, MM, true, true>(a, t, bufs, exch, dmin, dmax, bad, nonfinite);
+                    blk_fwd_unit<N, MM, true, true, double, double>(a, t, bufs, exch, dmin, dmax, bad, nonfinite);
                 else
-                    blk_fwd_unit<N, MM, false, true>(a, t, bufs, exch, dmin, dmax, bad, nonfinite);
+                    blk_fwd_unit<N, MM, false, true, double, double>(a, t, bufs, exch, dmin, dmax, bad, nonfinite);
                 __syncthreads();
             }
         }
@@ -444,14 +452,14 @@ __global__ __launch_bounds__(BGeo<N>::TB) void k_blk_fwd_tail(FwdTailArgs ta) {
     }
     reduce_slots(ta.slots, ta.nprev, dmin, dmax);
     block_minmax<BG::TB>(dmin, dmax, bad, nonfinite, ta.a.flags);
-    rank_flag(dmin, dmax, ta.a.flags);
+    rank_flag(dmin, dmax, ta.rank_tol, ta.a.flags);
 }
 
 // ------------------------------------------------------------ backward level
 
 // one block row (record t of level l); TBB threads, lane g < 3n+1 owns column g
 // of the R row: [R_ii | R_i,b | rho_i | R_i,a]
-template <int N, bool DO_Y, bool DO_COV>
+template <int N, bool DO_Y, bool DO_COV, class TR>
 __device__ __forceinline__ void blk_bwd_unit(const BwdArgs &a, int l, int64_t t, int64_t units,
                                              bool store_s, double *sm) {
     using BG = BGeo<N>;
@@ -466,12 +474,12 @@ __device__ __forceinline__ void blk_bwd_unit(const BwdArgs &a, int l, int64_t t,
     const int64_t i = ((2 * t + 1) << l) - 1;
     const int64_t aa = i - ((int64_t)1 << l), bb = i + ((int64_t)1 << l);
     const bool va = valid && aa >= 0, vb = valid && bb <= a.k;
-    const double *rec = a.rrows_all + (a.rec_off[l] + t) * BG::RREC;
+    const TR *rec = slot<TR>(a.rrows_all, a.rec_off[l] + t, BG::RREC);
 
     double x[N];
     if (gl < W) {
 #pragma unroll
-        for (int r = 0; r < N; ++r) x[r] = valid ? rec[r * W + gl] : (r == gl ? 1.0 : 0.0);
+        for (int r = 0; r < N; ++r) x[r] = valid ? double(rec[r * W + gl]) : (r == gl ? 1.0 : 0.0);
         if (gl < N) {
 #pragma unroll
             for (int r = 0; r < N; ++r) Rd[r * N + gl] = x[r];
@@ -588,11 +596,11 @@ struct BSmem {
     static constexpr int PER = N * N + N * (2 * N + 1) + N * N + 2 * N * N;
 };
 
-template <int N, bool DO_Y, bool DO_COV>
+template <int N, bool DO_Y, bool DO_COV, class TR>
 __global__ __launch_bounds__(BGeo<N>::TBB) void k_blk_backward(BwdArgs a) {
     __shared__ double sm[BSmem<N>::PER];
     const int l = a.level;
-    blk_bwd_unit<N, DO_Y, DO_COV>(a, l, blockIdx.x, (a.Nl[l] + 1) / 2, a.store_s && l >= 1, sm);
+    blk_bwd_unit<N, DO_Y, DO_COV, TR>(a, l, blockIdx.x, (a.Nl[l] + 1) / 2, a.store_s && l >= 1, sm);
 }
 
 template <int N, bool DO_Y, bool DO_COV>
@@ -601,7 +609,7 @@ __global__ __launch_bounds__(BGeo<N>::TBB) void k_blk_bwd_tail(BwdArgs a) {
     for (int l = a.level; l >= a.l_lo; --l) {
         const int64_t units = (a.Nl[l] + 1) / 2;
         for (int64_t t = 0; t < units; ++t)
-            blk_bwd_unit<N, DO_Y, DO_COV>(a, l, t, units, a.store_s && l >= 1, sm);
+            blk_bwd_unit<N, DO_Y, DO_COV, double>(a, l, t, units, a.store_s && l >= 1, sm);
         __threadfence();
         __syncthreads();
     }
@@ -609,14 +617,14 @@ __global__ __launch_bounds__(BGeo<N>::TBB) void k_blk_bwd_tail(BwdArgs a) {
 
 // -------------------------------------------------------------- dispatch
 
-template <int N, int MM, bool RAW>
+template <int N, int MM, bool RAW, class T, class TIN>
 static void launch_blk_fwd_t(const FwdArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((k_blk_forward<N, MM, RAW>), dim3((unsigned)a.units), dim3(BGeo<N>::TB), 0, s, a);
+    hipLaunchKernelGGL((k_blk_forward<N, MM, RAW, T, TIN>), dim3((unsigned)a.units), dim3(BGeo<N>::TB), 0, s, a);
 }
 
-template <int N, int MM, bool RAW>
+template <int N, int MM, bool RAW, class T, class TIN>
 static void launch_blk_fold_t(const FwdArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((k_blk_fold<N, MM, RAW>), dim3(1), dim3(BGeo<N>::TB), 0, s, a);
+    hipLaunchKernelGGL((k_blk_fold<N, MM, RAW, T, TIN>), dim3(1), dim3(BGeo<N>::TB), 0, s, a);
 }
 
 template <int N, int MM, bool RAW0>
@@ -624,10 +632,10 @@ static void launch_blk_fwd_tail_t(const FwdTailArgs &a, hipStream_t s) {
     hipLaunchKernelGGL((k_blk_fwd_tail<N, MM, RAW0>), dim3(1), dim3(BGeo<N>::TB), 0, s, a);
 }
 
-template <int N, bool Y, bool COV>
+template <int N, bool Y, bool COV, class TR>
 static void launch_blk_bwd_t(const BwdArgs &a, hipStream_t s) {
     const int64_t units = (a.Nl[a.level] + 1) / 2;
-    hipLaunchKernelGGL((k_blk_backward<N, Y, COV>), dim3((unsigned)units), dim3(BGeo<N>::TBB), 0, s, a);
+    hipLaunchKernelGGL((k_blk_backward<N, Y, COV, TR>), dim3((unsigned)units), dim3(BGeo<N>::TBB), 0, s, a);
 }
 
 template <int N, bool Y, bool COV>
@@ -639,14 +647,17 @@ template <int N, int MM>
 constexpr KernelSet make_blk_set() {
     return KernelSet{N,
                      MM,
-                     &launch_blk_fwd_t<N, MM, true>,
-                     &launch_blk_fwd_t<N, MM, false>,
-                     &launch_blk_fold_t<N, MM, true>,
-                     &launch_blk_fold_t<N, MM, false>,
+                     {&launch_blk_fwd_t<N, MM, true, double, double>, &launch_blk_fwd_t<N, MM, true, float, double>},
+                     {&launch_blk_fwd_t<N, MM, false, double, double>, &launch_blk_fwd_t<N, MM, false, float, float>,
+                      &launch_blk_fwd_t<N, MM, false, double, float>},
+                     {&launch_blk_fold_t<N, MM, true, double, double>, &launch_blk_fold_t<N, MM, true, float, double>},
+                     {&launch_blk_fold_t<N, MM, false, double, double>, &launch_blk_fold_t<N, MM, false, float, float>,
+                      &launch_blk_fold_t<N, MM, false, double, float>},
                      &launch_blk_fwd_tail_t<N, MM, true>,
                      &launch_blk_fwd_tail_t<N, MM, false>,
-                     {&launch_blk_bwd_t<N, true, false>, &launch_blk_bwd_t<N, false, true>,
-                      &launch_blk_bwd_t<N, true, true>},
+                     {{&launch_blk_bwd_t<N, true, false, double>, &launch_blk_bwd_t<N, true, false, float>},
+                      {&launch_blk_bwd_t<N, false, true, double>, &launch_blk_bwd_t<N, false, true, float>},
+                      {&launch_blk_bwd_t<N, true, true, double>, &launch_blk_bwd_t<N, true, true, float>}},
                      {&launch_blk_bwd_tail_t<N, true, false>, &launch_blk_bwd_tail_t<N, false, true>,
                       &launch_blk_bwd_tail_t<N, true, true>},
                      1,

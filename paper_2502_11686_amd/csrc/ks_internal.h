@@ -44,6 +44,7 @@ struct FwdTailArgs {
     int32_t l0, L;
     double *sys;      // reduced-system segment
     double *rrows;    // R-row record 0
+    double rank_tol;  // KS_E_RANK when min |R_pp| <= rank_tol * max |R_pp|
     const double *slots;  // per-block slots of the launches before the tail
     int64_t nprev;
     int64_t sys_off[kMaxLevels];
@@ -70,19 +71,27 @@ struct BwdArgs {
 
 enum BwdMode { BWD_Y = 0, BWD_COV = 1, BWD_BOTH = 2 };
 
+// precision variant of a forward launch: compute/storage type and the type of
+// the records it reads
+enum FwdVariant { FV_F64 = 0, FV_F32 = 1, FV_F64_FROM_F32 = 2 };
+
+using FwdFn = void (*)(const FwdArgs &, hipStream_t);
+using BwdFn = void (*)(const BwdArgs &, hipStream_t);
+using TailFn = void (*)(const FwdTailArgs &, hipStream_t);
+
 // kernels launched by the runtime for state dimension n, observation class mm
 struct KernelSet {
     int n, mm;
-    void (*fwd_raw)(const FwdArgs &, hipStream_t);
-    void (*fwd)(const FwdArgs &, hipStream_t);
-    void (*fold_raw)(const FwdArgs &, hipStream_t);   // last column of an odd level
-    void (*fold)(const FwdArgs &, hipStream_t);
-    void (*fwd_tail_raw)(const FwdTailArgs &, hipStream_t);  // tail starting at level 0
-    void (*fwd_tail)(const FwdTailArgs &, hipStream_t);
-    void (*bwd[3])(const BwdArgs &, hipStream_t);             // indexed by BwdMode
-    void (*bwd_tail[3])(const BwdArgs &, hipStream_t);
-    int upb_fwd;          // units per workgroup, per-level forward kernel
-    int upb_fwd_tail;     // units per pass of the forward tail
+    FwdFn fwd_raw[2];       // level 0 from the FP64 inputs: [FP64 | FP32]
+    FwdFn fwd[3];           // levels >= 1, indexed by FwdVariant
+    FwdFn fold_raw[2];      // last column of an odd level
+    FwdFn fold[3];
+    TailFn fwd_tail_raw;    // single-workgroup tail starting at level 0 (FP64)
+    TailFn fwd_tail;        // tail starting above level 0 (FP64 records in and out)
+    BwdFn bwd[3][2];        // [BwdMode][records FP64 | FP32]; arithmetic in FP64
+    BwdFn bwd_tail[3];      // FP64 records
+    int upb_fwd;            // units per workgroup, per-level forward kernel
+    int upb_fwd_tail;       // units per pass of the forward tail
     int upb_bwd[3];
     int upb_bwd_tail[3];
 };

@@ -38,7 +38,7 @@ bool valid_desc(const ks_desc *d) {
     if (!d) return false;
     if (d->k < 0 || d->k > ((int64_t)1 << 40)) return false;
     if (d->n < 1 || d->m < 0) return false;
-    if (d->precision != KS_FP64) return false;
+    if (d->precision != KS_FP64 && d->precision != KS_FP32_FORM) return false;
     if ((d->K_layout != KS_COV_DENSE && d->K_layout != KS_COV_DIAG) ||
         (d->C_layout != KS_COV_DENSE && d->C_layout != KS_COV_DIAG))
         return false;
@@ -101,6 +101,7 @@ struct ks_plan {
     bool smoothed;
     unsigned host_flags;   // status word copied back after each call
     int tail_passes;       // single-workgroup tail: levels needing <= this many passes
+    int l_switch;          // FP32 form: levels below this one run in FP32 (0 = none)
     // instrumentation (ks_time_kernels)
     int time_kind;
     bool time_armed;       // events of the current call were recorded
@@ -156,7 +157,9 @@ void enqueue_forward(ks_plan *p, const double *H, const double *F, const double 
     ks::launch_clear_flags(flags, p->stream);
     mark(p, KS_TIME_FWD_ALL, 0);
     int l0 = tail_start(lo, p->kset->upb_fwd_tail, p->tail_passes, false);
-    if (l0 > lo.L) l0 = lo.L;  // the base level always runs in the tail kernel
+    const int ls = p->l_switch;
+    if (ls > 0 && l0 <= ls) l0 = ls + 1;  // the tail reads FP64 records only
+    if (l0 > lo.L) l0 = lo.L;             // the base level always runs in the tail kernel
     ks::FwdArgs a{};
     a.k = p->d.k;
     a.m = p->d.m;
@@ -174,9 +177,16 @@ void enqueue_forward(ks_plan *p, const double *H, const double *F, const double 
         a.slots = slots + 2 * lo.slot_off[l];
         const int64_t blocks = (a.units + p->kset->upb_fwd - 1) / p->kset->upb_fwd;
         a.fold_slot = a.slots + 2 * blocks;
+        // precision of this level: FP32 below the switch, FP64 from it on
+        const int v = l < ls ? ks::FV_F32 : (l == ls && l > 0 ? ks::FV_F64_FROM_F32 : ks::FV_F64);
         if (l == 0) mark(p, KS_TIME_FWD_LEVEL0, 0);
-        (l == 0 ? p->kset->fwd_raw : p->kset->fwd)(a, p->stream);
-        if (lo.Nl[l] & 1) (l == 0 ? p->kset->fold_raw : p->kset->fold)(a, p->stream);
+        if (l == 0) {
+            p->kset->fwd_raw[v == ks::FV_F32](a, p->stream);
+            if (lo.Nl[l] & 1) p->kset->fold_raw[v == ks::FV_F32](a, p->stream);
+        } else {
+            p->kset->fwd[v](a, p->stream);
+            if (lo.Nl[l] & 1) p->kset->fold[v](a, p->stream);
+        }
         if (l == 0) mark(p, KS_TIME_FWD_LEVEL0, 1);
     }
     ks::FwdTailArgs ta{};
@@ -187,6 +197,7 @@ void enqueue_forward(ks_plan *p, const double *H, const double *F, const double 
     ta.rrows = rrows;
     ta.slots = slots;
     ta.nprev = lo.slot_off[l0];
+    ta.rank_tol = 64.0 * (p->l_switch > 0 ? 1.1920928955078125e-07 : 2.220446049250313e-16);
     for (int l = 0; l <= lo.L; ++l) {
         ta.sys_off[l] = lo.sys_off[l];
         ta.rec_off[l] = lo.rec_off[l];
@@ -214,7 +225,8 @@ void enqueue_backward(ks_plan *p, double *u_out, double *cov_out) {
         b.rec_off[l] = lo.rec_off[l];
         b.Nl[l] = lo.Nl[l];
     }
-    const int l1 = tail_start(lo, p->kset->upb_bwd_tail[mode], p->tail_passes, true);
+    int l1 = tail_start(lo, p->kset->upb_bwd_tail[mode], p->tail_passes, true);
+    if (l1 < p->l_switch) l1 = p->l_switch;  // the tail reads FP64 records only
     mark(p, KS_TIME_BWD_ALL, 0);
     if (l1 <= lo.L) {
         b.level = lo.L;
@@ -227,7 +239,7 @@ void enqueue_backward(ks_plan *p, double *u_out, double *cov_out) {
         b.level = l;
         b.l_lo = l;
         if (l == 0) mark(p, KS_TIME_BWD_LEVEL0, 0);
-        p->kset->bwd[mode](b, p->stream);
+        p->kset->bwd[mode][l < p->l_switch ? 1 : 0](b, p->stream);
         if (l == 0) mark(p, KS_TIME_BWD_LEVEL0, 1);
     }
     mark(p, KS_TIME_BWD_ALL, 1);
@@ -298,6 +310,12 @@ ks_status ks_create(const ks_desc *desc, void *workspace, size_t ws_bytes, void 
     p->time_count = 0;
     p->tail_passes = 2;
     if (const char *e = std::getenv("KS_TAIL_PASSES")) p->tail_passes = std::atoi(e);
+    // FP32 form: levels with more than switch_cols columns run in FP32
+    int64_t switch_cols = 1024;
+    if (const char *e = std::getenv("KS_FP32_SWITCH")) switch_cols = std::atoll(e);
+    p->l_switch = 0;
+    if (desc->precision == KS_FP32_FORM)
+        while (p->l_switch < lo.L && lo.Nl[p->l_switch] > switch_cols) ++p->l_switch;
     *out = p;
     return KS_OK;
 }

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libks.so")
 
 KS_OK, KS_E_ARG, KS_E_WORKSPACE, KS_E_NOT_SPD, KS_E_RANK = 0, -1, -2, -3, -4
 KS_E_NONFINITE, KS_E_HIP, KS_E_ORDER = -5, -6, -7
-KS_FP64 = 0
+KS_FP64, KS_FP32_FORM = 0, 1
 KS_COV_DENSE, KS_COV_DIAG = 0, 1
 
 SYMBOLS = ("ks_workspace_bytes", "ks_supported", "ks_create", "ks_smooth", "ks_covariances",
@@ -86,14 +86,14 @@ def lib():
     return L
 
 
-def make_desc(k: int, n: int, m: int, K_diag: bool, C_diag: bool) -> Desc:
-    return Desc(k=int(k), n=int(n), m=int(m), precision=KS_FP64,
+def make_desc(k: int, n: int, m: int, K_diag: bool, C_diag: bool, fp32: bool = False) -> Desc:
+    return Desc(k=int(k), n=int(n), m=int(m), precision=KS_FP32_FORM if fp32 else KS_FP64,
                 K_layout=KS_COV_DIAG if K_diag else KS_COV_DENSE,
                 C_layout=KS_COV_DIAG if C_diag else KS_COV_DENSE, flags=0)
 
 
-def workspace_bytes(k: int, n: int, m: int, K_diag: bool, C_diag: bool) -> int:
-    d = make_desc(k, n, m, K_diag, C_diag)
+def workspace_bytes(k: int, n: int, m: int, K_diag: bool, C_diag: bool, fp32: bool = False) -> int:
+    d = make_desc(k, n, m, K_diag, C_diag, fp32)
     return int(lib().ks_workspace_bytes(ctypes.byref(d)))
 
 
@@ -124,12 +124,14 @@ class Plan:
     """A smoothing plan for one problem shape, owning its device workspace."""
 
     def __init__(self, k: int, n: int, m: int, K_diag: bool, C_diag: bool,
-                 device: Optional[torch.device] = None, stream: Optional[torch.cuda.Stream] = None):
+                 device: Optional[torch.device] = None, stream: Optional[torch.cuda.Stream] = None,
+                 fp32: bool = False):
         self.k, self.n, self.m = int(k), int(n), int(m)
         self.K_diag, self.C_diag = bool(K_diag), bool(C_diag)
+        self.fp32 = bool(fp32)
         self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
-        self._desc = make_desc(k, n, m, K_diag, C_diag)
+        self._desc = make_desc(k, n, m, K_diag, C_diag, fp32)
         L = lib()
         nbytes = int(L.ks_workspace_bytes(ctypes.byref(self._desc)))
         if nbytes == 0:
@@ -244,10 +246,10 @@ def to_device(p, device="cuda"):
     return tuple(t(a) for a in (p.H, p.F, p.c, p.K, p.G, p.o, p.C))
 
 
-def smooth_problem(p, want_cov: bool = True, device="cuda"):
+def smooth_problem(p, want_cov: bool = True, device="cuda", fp32: bool = False):
     """Convenience: smooth a generated problem; returns device tensors (u, cov)."""
     args = to_device(p, device)
-    plan = Plan(p.k, p.n, p.m, p.K_diag, p.C_diag, device=device)
+    plan = Plan(p.k, p.n, p.m, p.K_diag, p.C_diag, device=device, fp32=fp32)
     try:
         if want_cov:
             return plan.smooth_cov(*args)

@@ -1,0 +1,65 @@
+"""GPU: the FP32 form (FP32 elimination for the wide levels, FP64 top levels
+and FP64 back-substitution/SelInv products) against the FP64 oracle.
+
+Gate (no accuracy is fixed by the paper, which is all FP64): states normwise
+and covariance blocks (Frobenius, per block) within 1e-5 relative; the
+measured errors are printed."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import seq
+from paper_2502_11686_amd import gen, ks
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def run(p, fp32, monkeypatch=None, switch=None):
+    if monkeypatch is not None:
+        if switch is None:
+            monkeypatch.delenv("KS_FP32_SWITCH", raising=False)
+        else:
+            monkeypatch.setenv("KS_FP32_SWITCH", str(switch))
+    plan = ks.Plan(p.k, p.n, p.m, p.K_diag, p.C_diag, fp32=fp32)
+    try:
+        u, S = plan.smooth_cov(*ks.to_device(p))
+        torch.cuda.synchronize()
+        return u.cpu().numpy(), S.cpu().numpy()
+    finally:
+        plan.close()
+
+
+def errs(u, S, ref):
+    eu = float(np.max(np.abs(u - ref["u"])) / np.max(np.abs(ref["u"])))
+    es = float(np.max(np.linalg.norm(S - ref["cov"], axis=(1, 2)) / np.linalg.norm(ref["cov"], axis=(1, 2))))
+    return eu, es
+
+
+@pytest.mark.parametrize("n,m,cov", [(4, 2, "diag"), (6, 3, "dense"), (8, 4, "diag"), (12, 6, "dense"),
+                                     (16, 8, "diag"), (24, 12, "dense"), (32, 16, "diag"), (48, 24, "diag")])
+@pytest.mark.parametrize("switch", [4, 64])
+def test_fp32_form_small_switch(n, m, cov, switch, monkeypatch):
+    k = 700 if n <= 16 else 150
+    p = gen.make_problem(np.random.default_rng(n * 31 + switch), k, n, m, cov=cov)
+    ref = seq.smooth(p)
+    u, S = run(p, True, monkeypatch, switch)
+    eu, es = errs(u, S, ref)
+    print(f"n={n} switch={switch}: state {eu:.2e} cov {es:.2e}", flush=True)
+    assert eu < TOL and es < TOL
+    assert np.array_equal(S, np.swapaxes(S, 1, 2))
+    # no FP32 level at all: identical to the FP64 path
+    u64, S64 = run(p, False, monkeypatch, None)
+    u32, S32 = run(p, True, monkeypatch, 10 ** 9)
+    assert np.array_equal(u64, u32) and np.array_equal(S64, S32)
+
+
+@pytest.mark.parametrize("wid", [1, 2])
+def test_fp32_form_full_workload(wid, monkeypatch):
+    p = gen.workload(wid)
+    ref = seq.smooth(p)
+    u, S = run(p, True, monkeypatch, None)
+    eu, es = errs(u, S, ref)
+    print(f"workload {wid} FP32 form: state {eu:.2e} cov {es:.2e}", flush=True)
+    assert eu < TOL and es < TOL
