@@ -93,7 +93,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", type=int, default=1, choices=(0, 1, 2))
+    ap.add_argument("--workload", type=int, default=1, choices=(0, 1, 2, 3))
+    ap.add_argument("--problems", type=int, default=512, help="batched workload: number of problems")
     ap.add_argument("--k", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
@@ -108,6 +109,8 @@ def main():
 
     from paper_2502_11686_amd import gen, ks
 
+    if args.workload == 3:
+        return batch_bench(args)
     p = gen.workload(args.workload, k=args.k)
     dev = torch.device("cuda", 0)
     tens = ks.to_device(p, dev)
@@ -219,6 +222,66 @@ def main():
         out["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(out), flush=True)
     plan.close()
+
+
+def batch_bench(args):
+    """512 uneven problems (k log-uniform in [64, 16384], n in {4, 8, 16, 32},
+    m = n/2, diagonal covariances): one batched pass per step, FP64 and the
+    FP32 form; value = smoothed states of all problems per second."""
+    import numpy as np
+    import torch
+
+    from paper_2502_11686_amd import gen, ks
+
+    dev = torch.device("cuda", 0)
+    probs = gen.batch_workload(args.problems)
+    steps_total = sum(p.k + 1 for p in probs)
+    inputs = [ks.to_device(p, dev) for p in probs]
+    out = {}
+    for fp32 in (False, True):
+        b = ks.Batch([(p.k, p.n, p.m, p.K_diag, p.C_diag, fp32) for p in probs], device=dev)
+        us, covs = b.outputs(True)
+        for _ in range(max(1, args.warmup)):
+            b.smooth(inputs, us, covs)
+        torch.cuda.synchronize()
+        lat = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ts = time.perf_counter()
+            b.smooth(inputs, us, covs)
+            lat.append(time.perf_counter() - ts)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        err = None
+        if not args.no_check:
+            from oracle import seq
+            eu = es = 0.0
+            for i in range(0, len(probs), max(1, len(probs) // 16)):
+                ref = seq.smooth(probs[i])
+                u, S = us[i].cpu().numpy(), covs[i].cpu().numpy()
+                eu = max(eu, float(np.max(np.abs(u - ref["u"])) / np.max(np.abs(ref["u"]))))
+                es = max(es, float(np.max(np.linalg.norm(S - ref["cov"], axis=(1, 2)) /
+                                          np.linalg.norm(ref["cov"], axis=(1, 2)))))
+            err = dict(state=eu, cov=es, problems_checked=len(range(0, len(probs), max(1, len(probs) // 16))))
+        out["fp32_form" if fp32 else "fp64"] = dict(
+            value=steps_total * args.steps / el, ms_per_step=el / args.steps * 1e3,
+            p50_ms=float(np.percentile(np.array(lat) * 1e3, 50)),
+            p99_ms=float(np.percentile(np.array(lat) * 1e3, 99)), err_vs_oracle=err)
+        b.close()
+    line = {
+        "metric": "smoothed time steps/s incl. covariances, FP64 vs FP32 form; p50/p99 latency",
+        "value": out["fp64"]["value"], "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": out["fp64"]["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded generator; per-step F and G, diagonal covariances)",
+        "config": {"workload": f"{len(probs)} uneven problems, k log-uniform [64,16384], n in {{4,8,16,32}}, "
+                               "m=n/2, one batched pass (hipGraph)", "problems": len(probs),
+                   "states": steps_total},
+        "p50_ms": out["fp64"]["p50_ms"], "p99_ms": out["fp64"]["p99_ms"],
+        "err_vs_oracle": out["fp64"]["err_vs_oracle"], "fp32_form": out["fp32_form"],
+        "roofline": None,
+    }
+    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

@@ -165,6 +165,43 @@ typedef enum {
 ks_status ks_time_kernels(ks_plan *plan, int32_t kind);
 ks_status ks_kernel_time(const ks_plan *plan, double *total_ms, int64_t *count);
 
+/* ---------------------------------------------------------------- batches
+ *
+ * Many independent problems (any mix of k, n, m, layouts and precision forms)
+ * smoothed together.  Every forward and backward level step is one launch per
+ * kernel class (state dimension n, observation class) and precision variant,
+ * covering that level of every problem that has it; each problem's top levels
+ * run as one workgroup of a single launch.  Each problem follows exactly the
+ * schedule a single plan would, so its results are bitwise those of
+ * ks_smooth_cov / ks_smooth on it alone.  The launch sequence is captured in a
+ * hipGraph on the first call with a given set of pointers and replayed while
+ * the pointers stay the same (set KS_NO_GRAPH=1 before ks_batch_create to
+ * launch eagerly). */
+typedef struct ks_batch ks_batch;
+
+/* device pointers of one problem, layouts as for ks_smooth_cov */
+typedef struct {
+    const double *H, *F, *c, *K, *G, *o, *C;
+    double *u_out;
+    double *cov_out;   /* may be NULL when want_cov == 0 */
+} ks_io;
+
+/* Exact device-workspace bytes for the batch, or 0 if any description is
+ * invalid or unsupported.  Host-only. */
+size_t ks_batch_workspace_bytes(int32_t count, const ks_desc *descs);
+
+/* Create a batch over caller-owned workspace (256-byte aligned) and stream. */
+ks_status ks_batch_create(int32_t count, const ks_desc *descs, void *workspace, size_t ws_bytes,
+                          void *hip_stream, ks_batch **out);
+
+/* Smooth every problem (states, plus covariances when want_cov != 0);
+ * synchronous.  statuses (count entries, may be NULL) receives each
+ * problem's status; the return value is KS_OK or the first error. */
+ks_status ks_batch_smooth(ks_batch *batch, const ks_io *io, int32_t want_cov,
+                          ks_status *statuses);
+
+ks_status ks_batch_destroy(ks_batch *batch);
+
 #ifdef __cplusplus
 }
 #endif

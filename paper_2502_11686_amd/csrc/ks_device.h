@@ -585,25 +585,28 @@ __device__ __forceinline__ void rank_flag(double dmin, double dmax, double tol, 
 }
 
 // one forward level, one unit per G lanes, many workgroups
-template <int N, int MM, bool RAW, class T, class TIN>
-__global__ __launch_bounds__(kBlock) void k_forward(FwdArgs a) {
+template <int N, int MM, bool RAW, class T, class TIN, bool BATCH>
+__global__ __launch_bounds__(kBlock) void k_forward(FwdArgs a0, const FwdArgs *tab, BlockMap bm) {
+    const FwdArgs &a = BATCH ? tab[bm.item[blockIdx.x]] : a0;
+    const int64_t blk = BATCH ? bm.blk[blockIdx.x] : (int64_t)blockIdx.x;
     const Grp<N> g;
     bool bad = false, nonfinite = false;
     double dmin = INFINITY, dmax = 0.0;
-    const int64_t t = (int64_t)blockIdx.x * Geo<N>::UPB + g.ui;
+    const int64_t t = blk * Geo<N>::UPB + g.ui;
     fwd_unit<N, MM, RAW, false, T, TIN>(a, t, g.in, g.gl, g.gbase, dmin, dmax, bad, nonfinite);
     block_minmax<kBlock>(dmin, dmax, bad, nonfinite, a.flags);
     if (threadIdx.x == 0) {
-        a.slots[2 * blockIdx.x] = dmin;
-        a.slots[2 * blockIdx.x + 1] = dmax;
+        a.slots[2 * blk] = dmin;
+        a.slots[2 * blk + 1] = dmax;
     }
 }
 
 // The fold of a level with N_l odd, after that level's k_forward: one unit
 // reloads the last unit's step-3 triangle, eliminates the last column and
 // re-triangularizes.  Writes one slot (a.fold_slot).
-template <int N, int MM, bool RAW, class T, class TIN>
-__global__ __launch_bounds__(kBlock) void k_fold(FwdArgs a) {
+template <int N, int MM, bool RAW, class T, class TIN, bool BATCH>
+__global__ __launch_bounds__(kBlock) void k_fold(FwdArgs a0, const FwdArgs *tab, BlockMap bm) {
+    const FwdArgs &a = BATCH ? tab[bm.item[blockIdx.x]] : a0;
     using GE = Geo<N>;
     const Grp<N> g;
     const bool valid = g.in && g.ui == 0;
@@ -635,8 +638,10 @@ __global__ __launch_bounds__(kBlock) void k_fold(FwdArgs a) {
 // recursion): each level is a loop of unit passes, levels are separated by a
 // device-scope fence and a workgroup barrier.  Ends with the rank test over
 // the per-block slots of the earlier launches and its own diagonal.
-template <int N, int MM, bool RAW0>
-__global__ __launch_bounds__(kTailBlock) void k_fwd_tail(FwdTailArgs ta) {
+template <int N, int MM, bool RAW0, bool BATCH>
+__global__ __launch_bounds__(kTailBlock) void k_fwd_tail(FwdTailArgs ta0, const FwdTailArgs *tab,
+                                                       BlockMap bm) {
+    const FwdTailArgs &ta = BATCH ? tab[bm.item[blockIdx.x]] : ta0;
     using GE = Geo<N>;
     constexpr int UPB = (kTailBlock / 64) * GE::UPW;
     const Grp<N> g;
@@ -849,20 +854,23 @@ __device__ __forceinline__ void bwd_unit(const BwdArgs &a, int l, int64_t t, int
     __syncthreads();  // the LDS region is reused by the next call
 }
 
-template <int N, bool DO_Y, bool DO_COV, class TR>
-__global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a) {
+template <int N, bool DO_Y, bool DO_COV, class TR, bool BATCH>
+__global__ __launch_bounds__(kBlock) void k_backward(BwdArgs a0, const BwdArgs *tab, BlockMap bm) {
     using SM = BwdSmem<N, DO_Y, DO_COV>;
+    const BwdArgs &a = BATCH ? tab[bm.item[blockIdx.x]] : a0;
     __shared__ double smem[Geo<N>::UPB * SM::PER];
     const Grp<N> g;
-    const int l = a.level;
-    const int64_t t = (int64_t)blockIdx.x * Geo<N>::UPB + g.ui;
+    const int l = BATCH ? bm.level[blockIdx.x] : a.level;
+    const int64_t blk = BATCH ? bm.blk[blockIdx.x] : (int64_t)blockIdx.x;
+    const int64_t t = blk * Geo<N>::UPB + g.ui;
     bwd_unit<N, DO_Y, DO_COV, TR>(a, l, t, (a.Nl[l] + 1) / 2, a.store_s && l >= 1, g.in, g.gl,
                               smem + g.ui * SM::PER);
 }
 
 // levels a.level down to a.l_lo in one workgroup of TB threads
-template <int N, bool DO_Y, bool DO_COV, int TB>
-__global__ __launch_bounds__(TB) void k_bwd_tail(BwdArgs a) {
+template <int N, bool DO_Y, bool DO_COV, int TB, bool BATCH>
+__global__ __launch_bounds__(TB) void k_bwd_tail(BwdArgs a0, const BwdArgs *tab, BlockMap bm) {
+    const BwdArgs &a = BATCH ? tab[bm.item[blockIdx.x]] : a0;
     using SM = BwdSmem<N, DO_Y, DO_COV>;
     constexpr int UPB = (TB / 64) * Geo<N>::UPW;
     __shared__ double smem[UPB * SM::PER];
@@ -889,30 +897,66 @@ struct BwdTailBlock {
 template <int N, int MM, bool RAW, class T, class TIN>
 static void launch_fwd_t(const FwdArgs &a, hipStream_t s) {
     const int64_t blocks = (a.units + Geo<N>::UPB - 1) / Geo<N>::UPB;
-    hipLaunchKernelGGL((k_forward<N, MM, RAW, T, TIN>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_forward<N, MM, RAW, T, TIN, false>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                       a, nullptr, BlockMap{});
+}
+
+template <int N, int MM, bool RAW, class T, class TIN>
+static void launch_fwd_bt(const FwdArgs *tab, BlockMap bm, int64_t blocks, hipStream_t s) {
+    hipLaunchKernelGGL((k_forward<N, MM, RAW, T, TIN, true>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                       FwdArgs{}, tab, bm);
 }
 
 template <int N, int MM, bool RAW, class T, class TIN>
 static void launch_fold_t(const FwdArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((k_fold<N, MM, RAW, T, TIN>), dim3(1), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_fold<N, MM, RAW, T, TIN, false>), dim3(1), dim3(kBlock), 0, s, a, nullptr,
+                       BlockMap{});
+}
+
+template <int N, int MM, bool RAW, class T, class TIN>
+static void launch_fold_bt(const FwdArgs *tab, BlockMap bm, int64_t blocks, hipStream_t s) {
+    hipLaunchKernelGGL((k_fold<N, MM, RAW, T, TIN, true>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                       FwdArgs{}, tab, bm);
 }
 
 template <int N, int MM, bool RAW0>
 static void launch_fwd_tail_t(const FwdTailArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((k_fwd_tail<N, MM, RAW0>), dim3(1), dim3(kTailBlock), 0, s, a);
+    hipLaunchKernelGGL((k_fwd_tail<N, MM, RAW0, false>), dim3(1), dim3(kTailBlock), 0, s, a, nullptr,
+                       BlockMap{});
+}
+
+template <int N, int MM, bool RAW0>
+static void launch_fwd_tail_bt(const FwdTailArgs *tab, BlockMap bm, int64_t blocks, hipStream_t s) {
+    hipLaunchKernelGGL((k_fwd_tail<N, MM, RAW0, true>), dim3((unsigned)blocks), dim3(kTailBlock), 0, s,
+                       FwdTailArgs{}, tab, bm);
 }
 
 template <int N, bool Y, bool COV, class TR>
 static void launch_bwd_t(const BwdArgs &a, hipStream_t s) {
     const int64_t units = (a.Nl[a.level] + 1) / 2;
     const int64_t blocks = (units + Geo<N>::UPB - 1) / Geo<N>::UPB;
-    hipLaunchKernelGGL((k_backward<N, Y, COV, TR>), dim3((unsigned)blocks), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((k_backward<N, Y, COV, TR, false>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                       a, nullptr, BlockMap{});
+}
+
+template <int N, bool Y, bool COV, class TR>
+static void launch_bwd_bt(const BwdArgs *tab, BlockMap bm, int64_t blocks, hipStream_t s) {
+    hipLaunchKernelGGL((k_backward<N, Y, COV, TR, true>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
+                       BwdArgs{}, tab, bm);
 }
 
 template <int N, bool Y, bool COV>
 static void launch_bwd_tail_t(const BwdArgs &a, hipStream_t s) {
     constexpr int TB = BwdTailBlock<N, Y, COV>::TB;
-    hipLaunchKernelGGL((k_bwd_tail<N, Y, COV, TB>), dim3(1), dim3(TB), 0, s, a);
+    hipLaunchKernelGGL((k_bwd_tail<N, Y, COV, TB, false>), dim3(1), dim3(TB), 0, s, a, nullptr,
+                       BlockMap{});
+}
+
+template <int N, bool Y, bool COV>
+static void launch_bwd_tail_bt(const BwdArgs *tab, BlockMap bm, int64_t blocks, hipStream_t s) {
+    constexpr int TB = BwdTailBlock<N, Y, COV>::TB;
+    hipLaunchKernelGGL((k_bwd_tail<N, Y, COV, TB, true>), dim3((unsigned)blocks), dim3(TB), 0, s,
+                       BwdArgs{}, tab, bm);
 }
 
 // variants: forward [FP64 | FP32 | FP64 from FP32 records (switch level)],
@@ -934,6 +978,19 @@ constexpr KernelSet make_set() {
                       {&launch_bwd_t<N, true, true, double>, &launch_bwd_t<N, true, true, float>}},
                      {&launch_bwd_tail_t<N, true, false>, &launch_bwd_tail_t<N, false, true>,
                       &launch_bwd_tail_t<N, true, true>},
+                     {&launch_fwd_bt<N, MM, true, double, double>, &launch_fwd_bt<N, MM, true, float, double>},
+                     {&launch_fwd_bt<N, MM, false, double, double>, &launch_fwd_bt<N, MM, false, float, float>,
+                      &launch_fwd_bt<N, MM, false, double, float>},
+                     {&launch_fold_bt<N, MM, true, double, double>, &launch_fold_bt<N, MM, true, float, double>},
+                     {&launch_fold_bt<N, MM, false, double, double>, &launch_fold_bt<N, MM, false, float, float>,
+                      &launch_fold_bt<N, MM, false, double, float>},
+                     &launch_fwd_tail_bt<N, MM, true>,
+                     &launch_fwd_tail_bt<N, MM, false>,
+                     {{&launch_bwd_bt<N, true, false, double>, &launch_bwd_bt<N, true, false, float>},
+                      {&launch_bwd_bt<N, false, true, double>, &launch_bwd_bt<N, false, true, float>},
+                      {&launch_bwd_bt<N, true, true, double>, &launch_bwd_bt<N, true, true, float>}},
+                     {&launch_bwd_tail_bt<N, true, false>, &launch_bwd_tail_bt<N, false, true>,
+                      &launch_bwd_tail_bt<N, true, true>},
                      Geo<N>::UPB,
                      (kTailBlock / 64) * Geo<N>::UPW,
                      {Geo<N>::UPB, Geo<N>::UPB, Geo<N>::UPB},

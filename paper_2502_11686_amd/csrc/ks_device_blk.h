@@ -350,24 +350,28 @@ __device__ __forceinline__ void blk_fwd_unit(const FwdArgs &a, int64_t t, T *buf
     }
 }
 
-template <int N, int MM, bool RAW, class T, class TIN>
-__global__ __launch_bounds__(BGeo<N>::TB) void k_blk_forward(FwdArgs a) {
+template <int N, int MM, bool RAW, class T, class TIN, bool BATCH>
+__global__ __launch_bounds__(BGeo<N>::TB) void k_blk_forward(FwdArgs a0, const FwdArgs *tab,
+                                                             BlockMap bm) {
+    const FwdArgs &a = BATCH ? tab[bm.item[blockIdx.x]] : a0;
+    const int64_t blk = BATCH ? bm.blk[blockIdx.x] : (int64_t)blockIdx.x;
     constexpr int H = 2 * N;
     __shared__ T bufs[4 * (H + 2)];
     __shared__ T exch[N * (N + 1)];
     bool bad = false, nonfinite = false;
     double dmin = INFINITY, dmax = 0.0;
-    blk_fwd_unit<N, MM, RAW, false, T, TIN>(a, blockIdx.x, bufs, exch, dmin, dmax, bad, nonfinite);
+    blk_fwd_unit<N, MM, RAW, false, T, TIN>(a, blk, bufs, exch, dmin, dmax, bad, nonfinite);
     block_minmax<BGeo<N>::TB>(dmin, dmax, bad, nonfinite, a.flags);
     if (threadIdx.x == 0) {
-        a.slots[2 * blockIdx.x] = dmin;
-        a.slots[2 * blockIdx.x + 1] = dmax;
+        a.slots[2 * blk] = dmin;
+        a.slots[2 * blk + 1] = dmax;
     }
 }
 
 // the fold of an odd level after its k_blk_forward (one workgroup)
-template <int N, int MM, bool RAW, class T, class TIN>
-__global__ __launch_bounds__(BGeo<N>::TB) void k_blk_fold(FwdArgs a) {
+template <int N, int MM, bool RAW, class T, class TIN, bool BATCH>
+__global__ __launch_bounds__(BGeo<N>::TB) void k_blk_fold(FwdArgs a0, const FwdArgs *tab, BlockMap bm) {
+    const FwdArgs &a = BATCH ? tab[bm.item[blockIdx.x]] : a0;
     using BG = BGeo<N>;
     constexpr int H = 2 * N;
     __shared__ T bufs[4 * (H + 2)];
@@ -394,8 +398,10 @@ __global__ __launch_bounds__(BGeo<N>::TB) void k_blk_fold(FwdArgs a) {
 
 // forward levels l0..L in one workgroup (in this family only the base level,
 // or the whole problem when it is tiny), then the rank test
-template <int N, int MM, bool RAW0>
-__global__ __launch_bounds__(BGeo<N>::TB) void k_blk_fwd_tail(FwdTailArgs ta) {
+template <int N, int MM, bool RAW0, bool BATCH>
+__global__ __launch_bounds__(BGeo<N>::TB) void k_blk_fwd_tail(FwdTailArgs ta0, const FwdTailArgs *tab,
+                                                              BlockMap bm) {
+    const FwdTailArgs &ta = BATCH ? tab[bm.item[blockIdx.x]] : ta0;
     using BG = BGeo<N>;
     constexpr int H = 2 * N;
     __shared__ double bufs[4 * (H + 2)];
@@ -596,15 +602,20 @@ struct BSmem {
     static constexpr int PER = N * N + N * (2 * N + 1) + N * N + 2 * N * N;
 };
 
-template <int N, bool DO_Y, bool DO_COV, class TR>
-__global__ __launch_bounds__(BGeo<N>::TBB) void k_blk_backward(BwdArgs a) {
+template <int N, bool DO_Y, bool DO_COV, class TR, bool BATCH>
+__global__ __launch_bounds__(BGeo<N>::TBB) void k_blk_backward(BwdArgs a0, const BwdArgs *tab,
+                                                               BlockMap bm) {
+    const BwdArgs &a = BATCH ? tab[bm.item[blockIdx.x]] : a0;
     __shared__ double sm[BSmem<N>::PER];
-    const int l = a.level;
-    blk_bwd_unit<N, DO_Y, DO_COV, TR>(a, l, blockIdx.x, (a.Nl[l] + 1) / 2, a.store_s && l >= 1, sm);
+    const int l = BATCH ? bm.level[blockIdx.x] : a.level;
+    const int64_t blk = BATCH ? bm.blk[blockIdx.x] : (int64_t)blockIdx.x;
+    blk_bwd_unit<N, DO_Y, DO_COV, TR>(a, l, blk, (a.Nl[l] + 1) / 2, a.store_s && l >= 1, sm);
 }
 
-template <int N, bool DO_Y, bool DO_COV>
-__global__ __launch_bounds__(BGeo<N>::TBB) void k_blk_bwd_tail(BwdArgs a) {
+template <int N, bool DO_Y, bool DO_COV, bool BATCH>
+__global__ __launch_bounds__(BGeo<N>::TBB) void k_blk_bwd_tail(BwdArgs a0, const BwdArgs *tab,
+                                                               BlockMap bm) {
+    const BwdArgs &a = BATCH ? tab[bm.item[blockIdx.x]] : a0;
     __shared__ double sm[BSmem<N>::PER];
     for (int l = a.level; l >= a.l_lo; --l) {
         const int64_t units = (a.Nl[l] + 1) / 2;
@@ -619,28 +630,54 @@ __global__ __launch_bounds__(BGeo<N>::TBB) void k_blk_bwd_tail(BwdArgs a) {
 
 template <int N, int MM, bool RAW, class T, class TIN>
 static void launch_blk_fwd_t(const FwdArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((k_blk_forward<N, MM, RAW, T, TIN>), dim3((unsigned)a.units), dim3(BGeo<N>::TB), 0, s, a);
+    hipLaunchKernelGGL((k_blk_forward<N, MM, RAW, T, TIN, false>), dim3((unsigned)a.units), dim3(BGeo<N>::TB),
+                       0, s, a, nullptr, BlockMap{});
 }
-
+template <int N, int MM, bool RAW, class T, class TIN>
+static void launch_blk_fwd_bt(const FwdArgs *tab, BlockMap bm, int64_t blocks, hipStream_t s) {
+    hipLaunchKernelGGL((k_blk_forward<N, MM, RAW, T, TIN, true>), dim3((unsigned)blocks), dim3(BGeo<N>::TB),
+                       0, s, FwdArgs{}, tab, bm);
+}
 template <int N, int MM, bool RAW, class T, class TIN>
 static void launch_blk_fold_t(const FwdArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((k_blk_fold<N, MM, RAW, T, TIN>), dim3(1), dim3(BGeo<N>::TB), 0, s, a);
+    hipLaunchKernelGGL((k_blk_fold<N, MM, RAW, T, TIN, false>), dim3(1), dim3(BGeo<N>::TB), 0, s, a,
+                       nullptr, BlockMap{});
 }
-
+template <int N, int MM, bool RAW, class T, class TIN>
+static void launch_blk_fold_bt(const FwdArgs *tab, BlockMap bm, int64_t blocks, hipStream_t s) {
+    hipLaunchKernelGGL((k_blk_fold<N, MM, RAW, T, TIN, true>), dim3((unsigned)blocks), dim3(BGeo<N>::TB), 0,
+                       s, FwdArgs{}, tab, bm);
+}
 template <int N, int MM, bool RAW0>
 static void launch_blk_fwd_tail_t(const FwdTailArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((k_blk_fwd_tail<N, MM, RAW0>), dim3(1), dim3(BGeo<N>::TB), 0, s, a);
+    hipLaunchKernelGGL((k_blk_fwd_tail<N, MM, RAW0, false>), dim3(1), dim3(BGeo<N>::TB), 0, s, a, nullptr,
+                       BlockMap{});
 }
-
+template <int N, int MM, bool RAW0>
+static void launch_blk_fwd_tail_bt(const FwdTailArgs *tab, BlockMap bm, int64_t blocks, hipStream_t s) {
+    hipLaunchKernelGGL((k_blk_fwd_tail<N, MM, RAW0, true>), dim3((unsigned)blocks), dim3(BGeo<N>::TB), 0, s,
+                       FwdTailArgs{}, tab, bm);
+}
 template <int N, bool Y, bool COV, class TR>
 static void launch_blk_bwd_t(const BwdArgs &a, hipStream_t s) {
     const int64_t units = (a.Nl[a.level] + 1) / 2;
-    hipLaunchKernelGGL((k_blk_backward<N, Y, COV, TR>), dim3((unsigned)units), dim3(BGeo<N>::TBB), 0, s, a);
+    hipLaunchKernelGGL((k_blk_backward<N, Y, COV, TR, false>), dim3((unsigned)units), dim3(BGeo<N>::TBB), 0,
+                       s, a, nullptr, BlockMap{});
 }
-
+template <int N, bool Y, bool COV, class TR>
+static void launch_blk_bwd_bt(const BwdArgs *tab, BlockMap bm, int64_t blocks, hipStream_t s) {
+    hipLaunchKernelGGL((k_blk_backward<N, Y, COV, TR, true>), dim3((unsigned)blocks), dim3(BGeo<N>::TBB), 0,
+                       s, BwdArgs{}, tab, bm);
+}
 template <int N, bool Y, bool COV>
 static void launch_blk_bwd_tail_t(const BwdArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((k_blk_bwd_tail<N, Y, COV>), dim3(1), dim3(BGeo<N>::TBB), 0, s, a);
+    hipLaunchKernelGGL((k_blk_bwd_tail<N, Y, COV, false>), dim3(1), dim3(BGeo<N>::TBB), 0, s, a, nullptr,
+                       BlockMap{});
+}
+template <int N, bool Y, bool COV>
+static void launch_blk_bwd_tail_bt(const BwdArgs *tab, BlockMap bm, int64_t blocks, hipStream_t s) {
+    hipLaunchKernelGGL((k_blk_bwd_tail<N, Y, COV, true>), dim3((unsigned)blocks), dim3(BGeo<N>::TBB), 0, s,
+                       BwdArgs{}, tab, bm);
 }
 
 template <int N, int MM>
@@ -660,6 +697,19 @@ constexpr KernelSet make_blk_set() {
                       {&launch_blk_bwd_t<N, true, true, double>, &launch_blk_bwd_t<N, true, true, float>}},
                      {&launch_blk_bwd_tail_t<N, true, false>, &launch_blk_bwd_tail_t<N, false, true>,
                       &launch_blk_bwd_tail_t<N, true, true>},
+                     {&launch_blk_fwd_bt<N, MM, true, double, double>, &launch_blk_fwd_bt<N, MM, true, float, double>},
+                     {&launch_blk_fwd_bt<N, MM, false, double, double>, &launch_blk_fwd_bt<N, MM, false, float, float>,
+                      &launch_blk_fwd_bt<N, MM, false, double, float>},
+                     {&launch_blk_fold_bt<N, MM, true, double, double>, &launch_blk_fold_bt<N, MM, true, float, double>},
+                     {&launch_blk_fold_bt<N, MM, false, double, double>, &launch_blk_fold_bt<N, MM, false, float, float>,
+                      &launch_blk_fold_bt<N, MM, false, double, float>},
+                     &launch_blk_fwd_tail_bt<N, MM, true>,
+                     &launch_blk_fwd_tail_bt<N, MM, false>,
+                     {{&launch_blk_bwd_bt<N, true, false, double>, &launch_blk_bwd_bt<N, true, false, float>},
+                      {&launch_blk_bwd_bt<N, false, true, double>, &launch_blk_bwd_bt<N, false, true, float>},
+                      {&launch_blk_bwd_bt<N, true, true, double>, &launch_blk_bwd_bt<N, true, true, float>}},
+                     {&launch_blk_bwd_tail_bt<N, true, false>, &launch_blk_bwd_tail_bt<N, false, true>,
+                      &launch_blk_bwd_tail_bt<N, true, true>},
                      1,
                      0,
                      {1, 1, 1},

@@ -44,4 +44,13 @@ void launch_clear_flags(unsigned *flags, hipStream_t s) {
     hipLaunchKernelGGL(k_clear_flags, dim3(1), dim3(64), 0, s, flags);
 }
 
+__global__ void k_clear_flags_n(unsigned *flags, int32_t count) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) flags[i] = 0u;
+}
+
+void launch_clear_flags_n(unsigned *flags, int32_t count, hipStream_t s) {
+    hipLaunchKernelGGL(k_clear_flags_n, dim3((count + 255) / 256), dim3(256), 0, s, flags, count);
+}
+
 }  // namespace ks

@@ -79,6 +79,18 @@ using FwdFn = void (*)(const FwdArgs &, hipStream_t);
 using BwdFn = void (*)(const BwdArgs &, hipStream_t);
 using TailFn = void (*)(const FwdTailArgs &, hipStream_t);
 
+// Batched launches: workgroup b of a launch takes its arguments from table
+// entry item[b]; blk[b] is its block (or record-pass) index within that
+// problem's level and level[b] the level (backward launches).
+struct BlockMap {
+    const int32_t *item;
+    const int64_t *blk;
+    const int32_t *level;
+};
+using FwdBFn = void (*)(const FwdArgs *, BlockMap, int64_t blocks, hipStream_t);
+using BwdBFn = void (*)(const BwdArgs *, BlockMap, int64_t blocks, hipStream_t);
+using TailBFn = void (*)(const FwdTailArgs *, BlockMap, int64_t blocks, hipStream_t);
+
 // kernels launched by the runtime for state dimension n, observation class mm
 struct KernelSet {
     int n, mm;
@@ -90,6 +102,15 @@ struct KernelSet {
     TailFn fwd_tail;        // tail starting above level 0 (FP64 records in and out)
     BwdFn bwd[3][2];        // [BwdMode][records FP64 | FP32]; arithmetic in FP64
     BwdFn bwd_tail[3];      // FP64 records
+    // the same kernels driven by work tables (one launch for many problems)
+    FwdBFn fwd_raw_b[2];
+    FwdBFn fwd_b[3];
+    FwdBFn fold_raw_b[2];
+    FwdBFn fold_b[3];
+    TailBFn fwd_tail_raw_b;
+    TailBFn fwd_tail_b;
+    BwdBFn bwd_b[3][2];
+    BwdBFn bwd_tail_b[3];
     int upb_fwd;            // units per workgroup, per-level forward kernel
     int upb_fwd_tail;       // units per pass of the forward tail
     int upb_bwd[3];
@@ -105,5 +126,6 @@ struct KernelSetList {
 const KernelSet *find_kernels(int n, int m);
 
 void launch_clear_flags(unsigned *flags, hipStream_t s);
+void launch_clear_flags_n(unsigned *flags, int32_t count, hipStream_t s);
 
 }  // namespace ks

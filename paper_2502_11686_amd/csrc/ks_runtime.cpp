@@ -9,9 +9,11 @@
 // by level (ceil(N_l / 2) records at level l).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdlib>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "ks.h"
 #include "ks_internal.h"
@@ -414,6 +416,455 @@ ks_status ks_kernel_time(const ks_plan *p, double *total_ms, int64_t *count) {
     if (!p || !total_ms || !count) return KS_E_ARG;
     *total_ms = p->time_ms;
     *count = p->time_count;
+    return KS_OK;
+}
+
+}  // extern "C"
+
+// ====================================================================== batch
+//
+// Many problems (any mix of n, m, k, covariance layouts and precision forms)
+// advanced together: every forward level step is one launch per kernel class
+// (n, observation class) and precision variant covering the units of that
+// level of every problem still above its tail; each problem's top levels run
+// as one workgroup of a single tail launch; the backward mirrors it.  The
+// schedule of each problem is exactly that of a single plan, so its results
+// are bitwise those of ks_smooth_cov on it alone.  Launch arguments live in
+// device tables (one upload per set of input/output pointers) and the launch
+// sequence is captured once in a hipGraph and replayed.
+
+namespace {
+
+struct BatchProblem {
+    ks_desc d;
+    const ks::KernelSet *kset;
+    Layout lo;
+    size_t ws_off;  // of the problem's region in the workspace
+    int l_switch;   // levels below run in FP32 (FP32 form)
+    int l0;         // first forward level in the tail launch
+    int l1;         // lowest backward level in the tail launch
+    double rank_tol;
+};
+
+// one batched launch: a kernel and its block map (ranges in the table arrays)
+struct BLaunch {
+    enum Kind { FWD, FOLD, FTAIL, BWD, BTAIL } kind;
+    const ks::KernelSet *kset;
+    int variant;    // forward: FwdVariant (raw: 0/1); backward: record type
+    bool raw;       // level-0 forward / tail starting at level 0
+    int64_t map0, blocks;
+};
+
+template <class T>
+size_t tab_bytes(size_t n) { return align_up(sizeof(T) * n); }
+
+}  // namespace
+
+struct ks_batch {
+    hipStream_t stream;
+    char *ws;
+    int32_t count;
+    int mode_cov;  // mode the cached tables/graph were built for (-1 none)
+    std::vector<BatchProblem> probs;
+    std::vector<BLaunch> launches[2];  // [want_cov]
+    // host tables
+    std::vector<ks::FwdArgs> fwd_tab;
+    std::vector<ks::FwdTailArgs> tail_tab;
+    std::vector<ks::BwdArgs> bwd_tab;
+    std::vector<int32_t> map_item, map_level;
+    std::vector<int64_t> map_blk;
+    // device tables
+    size_t off_fwd, off_tail, off_bwd, off_item, off_blk, off_level, off_flags, total;
+    std::vector<ks_io> cached_io;
+    hipGraphExec_t exec;
+    bool have_exec;
+    bool use_graph;
+    std::vector<unsigned> host_flags;
+};
+
+namespace {
+
+template <class T>
+T *dptr(ks_batch *b, size_t off) { return reinterpret_cast<T *>(b->ws + off); }
+
+// Build the schedule: table entries with placeholder pointers (filled per call
+// by fill_tables) and the launch list, for want_cov = 0 and 1.
+void plan_batch(ks_batch *b) {
+    const int P = b->count;
+    b->fwd_tab.clear();
+    b->tail_tab.clear();
+    b->bwd_tab.assign(P, ks::BwdArgs{});
+    b->map_item.clear();
+    b->map_blk.clear();
+    b->map_level.clear();
+    auto add_map = [&](int32_t item, int64_t blk, int32_t lvl) {
+        b->map_item.push_back(item);
+        b->map_blk.push_back(blk);
+        b->map_level.push_back(lvl);
+    };
+    // distinct kernel sets in first-seen order
+    std::vector<const ks::KernelSet *> classes;
+    for (auto &pr : b->probs)
+        if (std::find(classes.begin(), classes.end(), pr.kset) == classes.end())
+            classes.push_back(pr.kset);
+    int maxL0 = 0, maxL1 = 0;
+    for (auto &pr : b->probs) {
+        maxL0 = std::max(maxL0, pr.l0);
+        maxL1 = std::max(maxL1, pr.l1);
+    }
+    // forward entries: one FwdArgs per (problem, level < l0)
+    std::vector<std::vector<int32_t>> fwd_index(P);
+    for (int i = 0; i < P; ++i) {
+        fwd_index[i].assign(b->probs[i].l0, -1);
+        for (int l = 0; l < b->probs[i].l0; ++l) {
+            fwd_index[i][l] = (int32_t)b->fwd_tab.size();
+            b->fwd_tab.push_back(ks::FwdArgs{});
+        }
+    }
+    for (int i = 0; i < P; ++i) b->tail_tab.push_back(ks::FwdTailArgs{});
+
+    for (int cov = 0; cov < 2; ++cov) {
+        auto &L = b->launches[cov];
+        L.clear();
+        const int mode = cov ? ks::BWD_BOTH : ks::BWD_Y;
+        for (int s = 0; s < maxL0; ++s) {
+            for (auto *cls : classes) {
+                for (int v = 0; v < 3; ++v) {
+                    BLaunch fl{BLaunch::FWD, cls, v, s == 0, (int64_t)b->map_item.size(), 0};
+                    for (int i = 0; i < P; ++i) {
+                        const BatchProblem &pr = b->probs[i];
+                        if (pr.kset != cls || s >= pr.l0) continue;
+                        const int vi = s < pr.l_switch ? ks::FV_F32
+                                     : (s == pr.l_switch && s > 0 ? ks::FV_F64_FROM_F32 : ks::FV_F64);
+                        if (vi != v) continue;
+                        const int64_t units = pr.lo.Nl[s] / 2;
+                        const int64_t blocks = (units + cls->upb_fwd - 1) / cls->upb_fwd;
+                        for (int64_t k = 0; k < blocks; ++k) add_map(fwd_index[i][s], k, s);
+                        fl.blocks += blocks;
+                    }
+                    if (fl.blocks) L.push_back(fl);
+                    BLaunch fo{BLaunch::FOLD, cls, v, s == 0, (int64_t)b->map_item.size(), 0};
+                    for (int i = 0; i < P; ++i) {
+                        const BatchProblem &pr = b->probs[i];
+                        if (pr.kset != cls || s >= pr.l0 || !(pr.lo.Nl[s] & 1)) continue;
+                        const int vi = s < pr.l_switch ? ks::FV_F32
+                                     : (s == pr.l_switch && s > 0 ? ks::FV_F64_FROM_F32 : ks::FV_F64);
+                        if (vi != v) continue;
+                        add_map(fwd_index[i][s], 0, s);
+                        fo.blocks += 1;
+                    }
+                    if (fo.blocks) L.push_back(fo);
+                }
+            }
+        }
+        for (auto *cls : classes) {
+            for (int raw = 1; raw >= 0; --raw) {
+                BLaunch t{BLaunch::FTAIL, cls, 0, raw == 1, (int64_t)b->map_item.size(), 0};
+                for (int i = 0; i < P; ++i) {
+                    const BatchProblem &pr = b->probs[i];
+                    if (pr.kset != cls || (pr.l0 == 0) != (raw == 1)) continue;
+                    add_map(i, 0, pr.l0);
+                    t.blocks += 1;
+                }
+                if (t.blocks) L.push_back(t);
+            }
+        }
+        for (auto *cls : classes) {
+            BLaunch t{BLaunch::BTAIL, cls, mode, false, (int64_t)b->map_item.size(), 0};
+            for (int i = 0; i < P; ++i) {
+                if (b->probs[i].kset != cls || b->probs[i].l1 > b->probs[i].lo.L) continue;
+                add_map(i, 0, b->probs[i].lo.L);
+                t.blocks += 1;
+            }
+            if (t.blocks) L.push_back(t);
+        }
+        for (int s = maxL1 - 1; s >= 0; --s) {
+            for (auto *cls : classes) {
+                for (int tr = 0; tr < 2; ++tr) {
+                    BLaunch bl{BLaunch::BWD, cls, tr, false, (int64_t)b->map_item.size(), 0};
+                    for (int i = 0; i < P; ++i) {
+                        const BatchProblem &pr = b->probs[i];
+                        if (pr.kset != cls || s >= std::min(pr.l1, pr.lo.L + 1)) continue;
+                        if ((s < pr.l_switch ? 1 : 0) != tr) continue;
+                        const int64_t units = (pr.lo.Nl[s] + 1) / 2;
+                        const int64_t blocks = (units + cls->upb_bwd[mode] - 1) / cls->upb_bwd[mode];
+                        for (int64_t k = 0; k < blocks; ++k) add_map(i, k, s);
+                        bl.blocks += blocks;
+                    }
+                    if (bl.blocks) L.push_back(bl);
+                }
+            }
+        }
+    }
+}
+
+// per-call contents of the tables (pointers of the io arrays)
+void fill_tables(ks_batch *b, const ks_io *io, bool cov) {
+    const int P = b->count;
+    int64_t fi = 0;
+    for (int i = 0; i < P; ++i) {
+        const BatchProblem &pr = b->probs[i];
+        const Layout &lo = pr.lo;
+        char *base = b->ws + pr.ws_off;
+        const int64_t n = pr.d.n, rrec = n * (3 * n + 1);
+        double *rrows = reinterpret_cast<double *>(base + lo.off_rrows);
+        double *sys = reinterpret_cast<double *>(base + lo.off_sys);
+        double *slots = reinterpret_cast<double *>(base + lo.off_slots);
+        unsigned *flags = dptr<unsigned>(b, b->off_flags) + i;
+        ks::FwdArgs a{};
+        a.k = pr.d.k;
+        a.m = pr.d.m;
+        a.K_diag = pr.d.K_layout == KS_COV_DIAG;
+        a.C_diag = pr.d.C_layout == KS_COV_DIAG;
+        a.H = io[i].H; a.F = io[i].F; a.c = io[i].c; a.K = io[i].K;
+        a.G = io[i].G; a.o = io[i].o; a.C = io[i].C;
+        a.flags = flags;
+        for (int l = 0; l < pr.l0; ++l) {
+            a.Nl = lo.Nl[l];
+            a.units = lo.Nl[l] / 2;
+            a.level = l;
+            a.sys_in = l >= 1 ? sys + lo.sys_off[l] : nullptr;
+            a.sys_out = sys + lo.sys_off[l + 1];
+            a.rrows = rrows + lo.rec_off[l] * rrec;
+            a.slots = slots + 2 * lo.slot_off[l];
+            const int64_t blocks = (a.units + pr.kset->upb_fwd - 1) / pr.kset->upb_fwd;
+            a.fold_slot = a.slots + 2 * blocks;
+            b->fwd_tab[fi++] = a;
+        }
+        ks::FwdTailArgs &ta = b->tail_tab[i];
+        ta = ks::FwdTailArgs{};
+        ta.a = a;
+        ta.l0 = pr.l0;
+        ta.L = lo.L;
+        ta.sys = sys;
+        ta.rrows = rrows;
+        ta.slots = slots;
+        ta.nprev = lo.slot_off[pr.l0];
+        ta.rank_tol = pr.rank_tol;
+        for (int l = 0; l <= lo.L; ++l) {
+            ta.sys_off[l] = lo.sys_off[l];
+            ta.rec_off[l] = lo.rec_off[l];
+            ta.Nl[l] = lo.Nl[l];
+        }
+        ks::BwdArgs &bw = b->bwd_tab[i];
+        bw = ks::BwdArgs{};
+        bw.k = pr.d.k;
+        bw.level = lo.L;
+        bw.l_lo = pr.l1;
+        bw.store_s = cov;
+        bw.rrows_all = rrows;
+        bw.u_in = io[i].u_out;
+        bw.u_out = io[i].u_out;
+        bw.cov = cov ? io[i].cov_out : nullptr;
+        bw.spm = reinterpret_cast<double *>(base + lo.off_spm);
+        bw.spm_first = lo.spm_first;
+        for (int l = 0; l <= lo.L; ++l) {
+            bw.rec_off[l] = lo.rec_off[l];
+            bw.Nl[l] = lo.Nl[l];
+        }
+    }
+}
+
+hipError_t upload_tables(ks_batch *b) {
+    hipError_t e;
+    if ((e = hipMemcpyAsync(dptr<char>(b, b->off_fwd), b->fwd_tab.data(), sizeof(ks::FwdArgs) * b->fwd_tab.size(),
+                            hipMemcpyHostToDevice, b->stream)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(dptr<char>(b, b->off_tail), b->tail_tab.data(), sizeof(ks::FwdTailArgs) * b->tail_tab.size(),
+                            hipMemcpyHostToDevice, b->stream)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(dptr<char>(b, b->off_bwd), b->bwd_tab.data(), sizeof(ks::BwdArgs) * b->bwd_tab.size(),
+                            hipMemcpyHostToDevice, b->stream)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(dptr<char>(b, b->off_item), b->map_item.data(), sizeof(int32_t) * b->map_item.size(),
+                            hipMemcpyHostToDevice, b->stream)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(dptr<char>(b, b->off_blk), b->map_blk.data(), sizeof(int64_t) * b->map_blk.size(),
+                            hipMemcpyHostToDevice, b->stream)) != hipSuccess) return e;
+    return hipMemcpyAsync(dptr<char>(b, b->off_level), b->map_level.data(), sizeof(int32_t) * b->map_level.size(),
+                          hipMemcpyHostToDevice, b->stream);
+}
+
+void enqueue_batch(ks_batch *b, bool cov) {
+    const int mode = cov ? ks::BWD_BOTH : ks::BWD_Y;
+    ks::launch_clear_flags_n(dptr<unsigned>(b, b->off_flags), b->count, b->stream);
+    const ks::FwdArgs *ft = dptr<ks::FwdArgs>(b, b->off_fwd);
+    const ks::FwdTailArgs *tt = dptr<ks::FwdTailArgs>(b, b->off_tail);
+    const ks::BwdArgs *bt = dptr<ks::BwdArgs>(b, b->off_bwd);
+    const int32_t *mi = dptr<int32_t>(b, b->off_item);
+    const int64_t *mb = dptr<int64_t>(b, b->off_blk);
+    const int32_t *ml = dptr<int32_t>(b, b->off_level);
+    for (const BLaunch &L : b->launches[cov]) {
+        const ks::BlockMap bm{mi + L.map0, mb + L.map0, ml + L.map0};
+        switch (L.kind) {
+        case BLaunch::FWD:
+            if (L.raw) L.kset->fwd_raw_b[L.variant == ks::FV_F32](ft, bm, L.blocks, b->stream);
+            else L.kset->fwd_b[L.variant](ft, bm, L.blocks, b->stream);
+            break;
+        case BLaunch::FOLD:
+            if (L.raw) L.kset->fold_raw_b[L.variant == ks::FV_F32](ft, bm, L.blocks, b->stream);
+            else L.kset->fold_b[L.variant](ft, bm, L.blocks, b->stream);
+            break;
+        case BLaunch::FTAIL:
+            (L.raw ? L.kset->fwd_tail_raw_b : L.kset->fwd_tail_b)(tt, bm, L.blocks, b->stream);
+            break;
+        case BLaunch::BTAIL:
+            L.kset->bwd_tail_b[mode](bt, bm, L.blocks, b->stream);
+            break;
+        case BLaunch::BWD:
+            L.kset->bwd_b[mode][L.variant](bt, bm, L.blocks, b->stream);
+            break;
+        }
+    }
+}
+
+bool same_io(const std::vector<ks_io> &a, const ks_io *io, int n) {
+    if ((int)a.size() != n) return false;
+    return std::memcmp(a.data(), io, sizeof(ks_io) * n) == 0;
+}
+
+}  // namespace
+
+extern "C" {
+
+static ks_status batch_setup(int32_t count, const ks_desc *descs, ks_batch *b, size_t *total) {
+    if (count <= 0 || !descs) return KS_E_ARG;
+    size_t off = 0;
+    b->count = count;
+    b->probs.resize(count);
+    int tail_passes = 2;
+    if (const char *e = std::getenv("KS_TAIL_PASSES")) tail_passes = std::atoi(e);
+    int64_t switch_cols = 1024;
+    if (const char *e = std::getenv("KS_FP32_SWITCH")) switch_cols = std::atoll(e);
+    for (int i = 0; i < count; ++i) {
+        BatchProblem &pr = b->probs[i];
+        pr.d = descs[i];
+        if (!valid_desc(&pr.d)) return KS_E_ARG;
+        pr.kset = ks::find_kernels(pr.d.n, pr.d.m);
+        if (!pr.kset) return KS_E_ARG;
+        if (!make_layout(&pr.d, pr.kset, &pr.lo)) return KS_E_ARG;
+        pr.ws_off = off;
+        off = align_up(off + pr.lo.total);
+        pr.l_switch = 0;
+        if (pr.d.precision == KS_FP32_FORM)
+            while (pr.l_switch < pr.lo.L && pr.lo.Nl[pr.l_switch] > switch_cols) ++pr.l_switch;
+        int l0 = tail_start(pr.lo, pr.kset->upb_fwd_tail, tail_passes, false);
+        if (pr.l_switch > 0 && l0 <= pr.l_switch) l0 = pr.l_switch + 1;
+        if (l0 > pr.lo.L) l0 = pr.lo.L;
+        pr.l0 = l0;
+        const int mode = ks::BWD_BOTH;  // the tail start does not depend on the mode's unit count here
+        int l1 = tail_start(pr.lo, pr.kset->upb_bwd_tail[mode], tail_passes, true);
+        if (l1 < pr.l_switch) l1 = pr.l_switch;
+        pr.l1 = l1;
+        pr.rank_tol = 64.0 * (pr.l_switch > 0 ? 1.1920928955078125e-07 : 2.220446049250313e-16);
+    }
+    plan_batch(b);
+    b->off_fwd = off;
+    off += tab_bytes<ks::FwdArgs>(b->fwd_tab.size());
+    b->off_tail = off;
+    off += tab_bytes<ks::FwdTailArgs>(b->tail_tab.size());
+    b->off_bwd = off;
+    off += tab_bytes<ks::BwdArgs>(b->bwd_tab.size());
+    b->off_item = off;
+    off += tab_bytes<int32_t>(b->map_item.size());
+    b->off_blk = off;
+    off += tab_bytes<int64_t>(b->map_blk.size());
+    b->off_level = off;
+    off += tab_bytes<int32_t>(b->map_level.size());
+    b->off_flags = off;
+    off += tab_bytes<unsigned>(count);
+    b->total = off;
+    *total = off;
+    return KS_OK;
+}
+
+size_t ks_batch_workspace_bytes(int32_t count, const ks_desc *descs) {
+    ks_batch tmp;
+    size_t total = 0;
+    if (batch_setup(count, descs, &tmp, &total) != KS_OK) return 0;
+    return total;
+}
+
+ks_status ks_batch_create(int32_t count, const ks_desc *descs, void *workspace, size_t ws_bytes,
+                          void *hip_stream, ks_batch **out) {
+    if (!out) return KS_E_ARG;
+    *out = nullptr;
+    ks_batch *b = new (std::nothrow) ks_batch;
+    if (!b) return KS_E_ARG;
+    size_t total = 0;
+    ks_status st = batch_setup(count, descs, b, &total);
+    if (st != KS_OK) {
+        delete b;
+        return st;
+    }
+    if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0 || ws_bytes < total) {
+        delete b;
+        return KS_E_WORKSPACE;
+    }
+    b->ws = static_cast<char *>(workspace);
+    b->stream = static_cast<hipStream_t>(hip_stream);
+    b->mode_cov = -1;
+    b->have_exec = false;
+    b->use_graph = !(std::getenv("KS_NO_GRAPH") && std::atoi(std::getenv("KS_NO_GRAPH")) != 0);
+    b->host_flags.assign(count, 0u);
+    *out = b;
+    return KS_OK;
+}
+
+ks_status ks_batch_smooth(ks_batch *b, const ks_io *io, int32_t want_cov, ks_status *statuses) {
+    if (!b || !io) return KS_E_ARG;
+    const bool cov = want_cov != 0;
+    for (int i = 0; i < b->count; ++i) {
+        const ks_desc &d = b->probs[i].d;
+        if (!io[i].u_out || (cov && !io[i].cov_out)) return KS_E_ARG;
+        if (d.k > 0 && (!io[i].F || !io[i].c || !io[i].K)) return KS_E_ARG;
+        if (d.m > 0 && (!io[i].G || !io[i].o || !io[i].C)) return KS_E_ARG;
+    }
+    hipError_t e;
+    const bool fresh = !(b->mode_cov == (int)cov && same_io(b->cached_io, io, b->count));
+    if (fresh) {
+        fill_tables(b, io, cov);
+        if ((e = upload_tables(b)) != hipSuccess) return KS_E_HIP;
+        b->cached_io.assign(io, io + b->count);
+        b->mode_cov = (int)cov;
+        if (b->have_exec) {
+            (void)hipGraphExecDestroy(b->exec);
+            b->have_exec = false;
+        }
+        if (b->use_graph) {
+            hipGraph_t g;
+            if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+                enqueue_batch(b, cov);
+                if (hipStreamEndCapture(b->stream, &g) == hipSuccess) {
+                    if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) == hipSuccess) b->have_exec = true;
+                    (void)hipGraphDestroy(g);
+                }
+            }
+            (void)hipGetLastError();
+        }
+    }
+    if (b->have_exec) {
+        if (hipGraphLaunch(b->exec, b->stream) != hipSuccess) return KS_E_HIP;
+    } else {
+        enqueue_batch(b, cov);
+    }
+    if (hipGetLastError() != hipSuccess) return KS_E_HIP;
+    e = hipMemcpyAsync(b->host_flags.data(), dptr<unsigned>(b, b->off_flags), sizeof(unsigned) * b->count,
+                       hipMemcpyDeviceToHost, b->stream);
+    if (e != hipSuccess) return KS_E_HIP;
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return KS_E_HIP;
+    ks_status worst = KS_OK;
+    for (int i = 0; i < b->count; ++i) {
+        const unsigned f = b->host_flags[i];
+        const ks_status s = (f & ks::FLAG_NOT_SPD) ? KS_E_NOT_SPD
+                          : (f & ks::FLAG_NONFINITE) ? KS_E_NONFINITE
+                          : (f & ks::FLAG_RANK) ? KS_E_RANK : KS_OK;
+        if (statuses) statuses[i] = s;
+        if (worst == KS_OK && s != KS_OK) worst = s;
+    }
+    return worst;
+}
+
+ks_status ks_batch_destroy(ks_batch *b) {
+    if (!b) return KS_E_ARG;
+    if (b->have_exec) (void)hipGraphExecDestroy(b->exec);
+    delete b;
     return KS_OK;
 }
 

@@ -24,7 +24,8 @@ KS_COV_DENSE, KS_COV_DIAG = 0, 1
 
 SYMBOLS = ("ks_workspace_bytes", "ks_supported", "ks_create", "ks_smooth", "ks_covariances",
            "ks_smooth_cov", "ks_destroy", "ks_status_string", "ks_plan_layout",
-           "ks_time_kernels", "ks_kernel_time")
+           "ks_time_kernels", "ks_kernel_time", "ks_batch_workspace_bytes", "ks_batch_create",
+           "ks_batch_smooth", "ks_batch_destroy")
 KS_TIME_OFF, KS_TIME_FWD_LEVEL0, KS_TIME_BWD_LEVEL0, KS_TIME_FWD_ALL, KS_TIME_BWD_ALL = range(5)
 
 
@@ -38,6 +39,10 @@ class Layout(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("rrow_offset", ctypes.c_int64),
                 ("rrow_stride", ctypes.c_int64), ("level_rec_offset", ctypes.c_int64 * 64),
                 ("level_columns", ctypes.c_int64 * 64)]
+
+
+class Io(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_void_p) for f in ("H", "F", "c", "K", "G", "o", "C", "u_out", "cov_out")]
 
 
 class KsError(RuntimeError):
@@ -82,6 +87,15 @@ def lib():
     L.ks_time_kernels.argtypes = [vp, ctypes.c_int32]
     L.ks_kernel_time.restype = ctypes.c_int
     L.ks_kernel_time.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+    L.ks_batch_workspace_bytes.restype = ctypes.c_size_t
+    L.ks_batch_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.POINTER(Desc)]
+    L.ks_batch_create.restype = ctypes.c_int
+    L.ks_batch_create.argtypes = [ctypes.c_int32, ctypes.POINTER(Desc), vp, ctypes.c_size_t, vp,
+                                  ctypes.POINTER(vp)]
+    L.ks_batch_smooth.restype = ctypes.c_int
+    L.ks_batch_smooth.argtypes = [vp, ctypes.POINTER(Io), ctypes.c_int32, ctypes.POINTER(ctypes.c_int)]
+    L.ks_batch_destroy.restype = ctypes.c_int
+    L.ks_batch_destroy.argtypes = [vp]
     _lib = L
     return L
 
@@ -256,3 +270,72 @@ def smooth_problem(p, want_cov: bool = True, device="cuda", fp32: bool = False):
         return plan.smooth(*args), None
     finally:
         plan.close()
+
+
+class Batch:
+    """Many problems smoothed together (one launch per level step and kernel
+    class; see include/ks.h).  ``shapes`` lists (k, n, m, K_diag, C_diag, fp32)."""
+
+    def __init__(self, shapes, device=None, stream=None):
+        self.shapes = [tuple(sh) for sh in shapes]
+        self.count = len(self.shapes)
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        descs = (Desc * self.count)(*[make_desc(k, n, m, kd, cd, f32) for (k, n, m, kd, cd, f32) in self.shapes])
+        self._descs = descs
+        L = lib()
+        nbytes = int(L.ks_batch_workspace_bytes(self.count, descs))
+        if nbytes == 0:
+            raise KsError(KS_E_ARG, "unsupported batch")
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        ptr = (self.workspace.data_ptr() + 255) // 256 * 256
+        self.ws_bytes = nbytes
+        h = ctypes.c_void_p()
+        st = L.ks_batch_create(self.count, descs, ctypes.c_void_p(ptr), nbytes,
+                               ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if st != KS_OK:
+            raise KsError(st, "ks_batch_create")
+        self._h = h
+
+    def outputs(self, want_cov=True):
+        us = [torch.empty((k + 1, n), dtype=torch.float64, device=self.device) for (k, n, *_r) in self.shapes]
+        covs = ([torch.empty((k + 1, n, n), dtype=torch.float64, device=self.device) for (k, n, *_r) in self.shapes]
+                if want_cov else [None] * self.count)
+        return us, covs
+
+    def smooth(self, inputs, us, covs=None, check=True):
+        """inputs[i] = (H, F, c, K, G, o, C) device tensors; writes us[i] (and
+        covs[i]); returns the per-problem status list."""
+        want_cov = covs is not None and all(c is not None for c in covs)
+        io = (Io * self.count)()
+        for i, ((k, n, m, kd, cd, _f), args) in enumerate(zip(self.shapes, inputs)):
+            H, F, c, K, G, o, C = args
+            _check(H, "H", (k, n, n), self.device, allow_none=True)
+            _check(F, "F", (k, n, n), self.device)
+            _check(c, "c", (k, n), self.device)
+            _check(K, "K", (k, n) if kd else (k, n, n), self.device)
+            _check(G, "G", (k + 1, m, n), self.device)
+            _check(o, "o", (k + 1, m), self.device)
+            _check(C, "C", (k + 1, m) if cd else (k + 1, m, m), self.device)
+            _check(us[i], "u_out", (k + 1, n), self.device)
+            if want_cov:
+                _check(covs[i], "cov_out", (k + 1, n, n), self.device)
+            io[i] = Io(*[None if t is None else t.data_ptr() for t in (H, F, c, K, G, o, C)],
+                       us[i].data_ptr(), covs[i].data_ptr() if want_cov else None)
+        st = (ctypes.c_int * self.count)()
+        r = lib().ks_batch_smooth(self._h, io, 1 if want_cov else 0, st)
+        statuses = list(st)
+        if check and r != KS_OK:
+            raise KsError(r, "ks_batch_smooth")
+        return statuses
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().ks_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
