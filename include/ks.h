@@ -64,7 +64,8 @@ typedef enum {
                                <= 64 eps max |R(q,q)|), e.g. k = 0 with m < n              */
     KS_E_NONFINITE = -5,    /* a NaN or Inf reached the R factor                           */
     KS_E_HIP = -6,          /* a HIP runtime call failed                                   */
-    KS_E_ORDER = -7         /* ks_covariances before a successful ks_smooth                */
+    KS_E_ORDER = -7,        /* ks_covariances before a successful ks_smooth                */
+    KS_E_BUSY = -8          /* engine: request does not fit in the free workspace now      */
 } ks_status;
 
 /* KS_FP64: every level in FP64.
@@ -201,6 +202,65 @@ ks_status ks_batch_smooth(ks_batch *batch, const ks_io *io, int32_t want_cov,
                           ks_status *statuses);
 
 ks_status ks_batch_destroy(ks_batch *batch);
+
+/* ---------------------------------------------------------------- engine
+ *
+ * Continuous batching for a stream of requests (one smoothing problem each,
+ * Section III's forward elimination, the back-substitution, and optionally
+ * Algorithm 2's covariances).  The engine owns a caller-given device
+ * workspace: 1/16 of it (at least 256 KiB) holds per-tick launch tables and
+ * 4096 status words, the rest is handed out as one region per admitted
+ * request, of exactly ks_workspace_bytes(desc) rounded up to 256 bytes (first
+ * fit over a free list that merges neighbours on release).  Each
+ * ks_engine_step advances every in-flight request by one step of its schedule
+ * -- one forward level (with its fold), the forward tail, the backward tail or
+ * one backward level -- with one launch per kernel class, step kind and
+ * precision variant covering all requests at that step, so a request admitted
+ * between ticks starts its level 0 in the same launches that carry older
+ * requests through their top levels.  A request's schedule is that of a
+ * single plan: its results are bitwise those of ks_smooth_cov (want_cov != 0)
+ * or ks_smooth on it alone.  Host-side state is not thread-safe: one thread
+ * drives an engine. */
+typedef struct ks_engine ks_engine;
+
+typedef struct {
+    int64_t inflight;         /* admitted, not finished                        */
+    int64_t retired_pending;  /* finished, not yet collected by ks_engine_retired */
+    int64_t ticks;            /* ks_engine_step calls that launched work       */
+    size_t region_bytes;      /* workspace bytes for request regions           */
+    size_t free_bytes;        /* of which free                                 */
+    size_t largest_free;      /* largest free extent (bounds the next admission) */
+} ks_engine_stats;
+
+/* workspace: device memory, 256-byte aligned, at least 1 MiB, caller-owned
+ * and kept alive until ks_engine_destroy; all work goes to hip_stream. */
+ks_status ks_engine_create(void *workspace, size_t ws_bytes, void *hip_stream, ks_engine **out);
+
+/* Admit one request; host-only (launches nothing).  io points to device
+ * arrays laid out as for ks_smooth_cov, which must stay valid and unchanged
+ * (outputs: untouched by the caller) until the request is retired.
+ * KS_E_BUSY: no free region, table share or status word right now -- retry
+ * after a step; KS_E_WORKSPACE: the request can never fit this engine;
+ * KS_E_ARG: bad description or pointer.  *ticket identifies the request. */
+ks_status ks_engine_submit(ks_engine *engine, const ks_desc *desc, const ks_io *io, int32_t want_cov,
+                           uint64_t *ticket);
+
+/* One tick (synchronous: returns after the tick's kernels have finished).
+ * *finished (may be NULL) receives the number of requests that completed;
+ * their regions are free again and their outputs are final. */
+ks_status ks_engine_step(ks_engine *engine, int32_t *finished);
+
+/* Collect up to capacity finished requests, oldest first: ticket and status
+ * (KS_OK, KS_E_NOT_SPD, KS_E_NONFINITE or KS_E_RANK, as ks_smooth_cov would
+ * return).  *count receives how many were written. */
+ks_status ks_engine_retired(ks_engine *engine, int32_t capacity, uint64_t *tickets,
+                            ks_status *statuses, int32_t *count);
+
+ks_status ks_engine_query(const ks_engine *engine, ks_engine_stats *out);
+
+/* Frees host state only; requests still in flight are abandoned (no kernels
+ * are outstanding between steps). */
+ks_status ks_engine_destroy(ks_engine *engine);
 
 #ifdef __cplusplus
 }

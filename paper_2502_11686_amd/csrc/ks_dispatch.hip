@@ -53,4 +53,13 @@ void launch_clear_flags_n(unsigned *flags, int32_t count, hipStream_t s) {
     hipLaunchKernelGGL(k_clear_flags_n, dim3((count + 255) / 256), dim3(256), 0, s, flags, count);
 }
 
+__global__ void k_clear_flags_list(unsigned *flags, const int32_t *idx, int32_t count) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count) flags[idx[i]] = 0u;
+}
+
+void launch_clear_flags_list(unsigned *flags, const int32_t *idx, int32_t count, hipStream_t s) {
+    hipLaunchKernelGGL(k_clear_flags_list, dim3((count + 255) / 256), dim3(256), 0, s, flags, idx, count);
+}
+
 }  // namespace ks

@@ -127,5 +127,7 @@ const KernelSet *find_kernels(int n, int m);
 
 void launch_clear_flags(unsigned *flags, hipStream_t s);
 void launch_clear_flags_n(unsigned *flags, int32_t count, hipStream_t s);
+// flags[idx[i]] = 0 for i < count (idx in device memory)
+void launch_clear_flags_list(unsigned *flags, const int32_t *idx, int32_t count, hipStream_t s);
 
 }  // namespace ks

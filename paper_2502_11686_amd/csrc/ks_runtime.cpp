@@ -378,6 +378,7 @@ const char *ks_status_string(ks_status s) {
     case KS_E_NONFINITE: return "non-finite value in the R factor";
     case KS_E_HIP: return "HIP runtime error";
     case KS_E_ORDER: return "ks_covariances called before a successful ks_smooth";
+    case KS_E_BUSY: return "the engine cannot admit the request now (workspace, tables or status words in use)";
     }
     return "unknown status";
 }
@@ -865,6 +866,494 @@ ks_status ks_batch_destroy(ks_batch *b) {
     if (!b) return KS_E_ARG;
     if (b->have_exec) (void)hipGraphExecDestroy(b->exec);
     delete b;
+    return KS_OK;
+}
+
+}  // extern "C"
+
+
+// ===================================================================== engine
+//
+// Continuous batching of served requests.  The engine sub-allocates one
+// region per admitted request from a caller-owned workspace (first fit over a
+// coalescing free list) and refuses a request whose region or launch-table
+// share does not fit right now (KS_E_BUSY: the caller keeps it queued).  Each
+// tick advances every in-flight request by one step of its schedule -- one
+// forward level with its fold, the forward tail, the backward tail or one
+// backward level -- with one launch per kernel class, step kind and variant
+// over all requests at that kind of step, so requests admitted while others
+// are deep in their recursion start level 0 in the same launches.  Every
+// request follows exactly the schedule of a single plan, so its results are
+// bitwise those of ks_smooth_cov (or ks_smooth) on it alone.
+
+#include <map>
+#include <set>
+
+namespace {
+
+struct EngReq {
+    uint64_t ticket;
+    BatchProblem pr;
+    ks_io io;
+    bool cov;
+    int32_t slot;      // status word
+    int phase;         // 0 forward levels, 1 forward tail, 2 backward tail, 3 backward levels
+    int level;         // current level of phases 0 and 3
+    bool fresh;        // status word not yet cleared
+    size_t tab_need;   // bound on this request's share of a tick's tables
+};
+
+constexpr int32_t kEngSlots = 4096;
+
+}  // namespace
+
+struct ks_engine {
+    char *ws;
+    size_t region_bytes;   // [0, region_bytes): request regions
+    size_t tab_off, tab_bytes;
+    unsigned *dflags;      // kEngSlots status words
+    hipStream_t stream;
+    std::map<size_t, size_t> free_list;  // offset -> bytes
+    std::set<int32_t> free_slots;
+    std::vector<EngReq> inflight;
+    std::vector<std::pair<uint64_t, ks_status>> retired;
+    size_t tab_used;       // sum of tab_need over in-flight requests
+    uint64_t next_ticket, ticks;
+    int tail_passes;
+    int64_t switch_cols;
+    std::vector<char> staging;
+    std::vector<unsigned> hflags;
+};
+
+namespace {
+
+constexpr size_t kEngTabFixed = 8 * kAlign;  // per-array alignment of one tick's tables
+
+bool eng_alloc(ks_engine *e, size_t bytes, size_t *off) {
+    for (auto it = e->free_list.begin(); it != e->free_list.end(); ++it) {
+        if (it->second < bytes) continue;
+        *off = it->first;
+        const size_t rest = it->second - bytes, at = it->first + bytes;
+        e->free_list.erase(it);
+        if (rest) e->free_list[at] = rest;
+        return true;
+    }
+    return false;
+}
+
+void eng_free(ks_engine *e, size_t off, size_t bytes) {
+    auto it = e->free_list.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != e->free_list.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        e->free_list.erase(nx);
+    }
+    if (it != e->free_list.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+            pv->second += it->second;
+            e->free_list.erase(it);
+        }
+    }
+}
+
+int fwd_variant(const BatchProblem &pr, int s) {
+    return s < pr.l_switch ? ks::FV_F32 : (s == pr.l_switch && s > 0 ? ks::FV_F64_FROM_F32 : ks::FV_F64);
+}
+
+int64_t fwd_blocks(const BatchProblem &pr, int l) {
+    return (pr.lo.Nl[l] / 2 + pr.kset->upb_fwd - 1) / pr.kset->upb_fwd;
+}
+
+int64_t bwd_blocks(const BatchProblem &pr, int l, int mode) {
+    const int upb = pr.kset->upb_bwd[mode];
+    return ((pr.lo.Nl[l] + 1) / 2 + upb - 1) / upb;
+}
+
+// the request's arguments (as fill_tables builds them for a batch)
+ks::FwdArgs eng_fwd_args(const ks_engine *e, const EngReq &r, int l) {
+    const BatchProblem &pr = r.pr;
+    const Layout &lo = pr.lo;
+    char *base = e->ws + pr.ws_off;
+    const int64_t n = pr.d.n, rrec = n * (3 * n + 1);
+    ks::FwdArgs a{};
+    a.k = pr.d.k;
+    a.m = pr.d.m;
+    a.K_diag = pr.d.K_layout == KS_COV_DIAG;
+    a.C_diag = pr.d.C_layout == KS_COV_DIAG;
+    a.H = r.io.H; a.F = r.io.F; a.c = r.io.c; a.K = r.io.K;
+    a.G = r.io.G; a.o = r.io.o; a.C = r.io.C;
+    a.flags = e->dflags + r.slot;
+    if (l >= 0) {
+        double *sys = reinterpret_cast<double *>(base + lo.off_sys);
+        double *slots = reinterpret_cast<double *>(base + lo.off_slots);
+        a.Nl = lo.Nl[l];
+        a.units = lo.Nl[l] / 2;
+        a.level = l;
+        a.sys_in = l >= 1 ? sys + lo.sys_off[l] : nullptr;
+        a.sys_out = sys + lo.sys_off[l + 1];
+        a.rrows = reinterpret_cast<double *>(base + lo.off_rrows) + lo.rec_off[l] * rrec;
+        a.slots = slots + 2 * lo.slot_off[l];
+        a.fold_slot = a.slots + 2 * fwd_blocks(pr, l);
+    }
+    return a;
+}
+
+ks::FwdTailArgs eng_tail_args(const ks_engine *e, const EngReq &r) {
+    const BatchProblem &pr = r.pr;
+    const Layout &lo = pr.lo;
+    char *base = e->ws + pr.ws_off;
+    ks::FwdTailArgs ta{};
+    ta.a = eng_fwd_args(e, r, -1);
+    ta.l0 = pr.l0;
+    ta.L = lo.L;
+    ta.sys = reinterpret_cast<double *>(base + lo.off_sys);
+    ta.rrows = reinterpret_cast<double *>(base + lo.off_rrows);
+    ta.slots = reinterpret_cast<double *>(base + lo.off_slots);
+    ta.nprev = lo.slot_off[pr.l0];
+    ta.rank_tol = pr.rank_tol;
+    for (int l = 0; l <= lo.L; ++l) {
+        ta.sys_off[l] = lo.sys_off[l];
+        ta.rec_off[l] = lo.rec_off[l];
+        ta.Nl[l] = lo.Nl[l];
+    }
+    return ta;
+}
+
+ks::BwdArgs eng_bwd_args(const ks_engine *e, const EngReq &r) {
+    const BatchProblem &pr = r.pr;
+    const Layout &lo = pr.lo;
+    char *base = e->ws + pr.ws_off;
+    ks::BwdArgs bw{};
+    bw.k = pr.d.k;
+    bw.level = lo.L;
+    bw.l_lo = pr.l1;
+    bw.store_s = r.cov;
+    bw.rrows_all = reinterpret_cast<double *>(base + lo.off_rrows);
+    bw.u_in = r.io.u_out;
+    bw.u_out = r.io.u_out;
+    bw.cov = r.cov ? r.io.cov_out : nullptr;
+    bw.spm = reinterpret_cast<double *>(base + lo.off_spm);
+    bw.spm_first = lo.spm_first;
+    for (int l = 0; l <= lo.L; ++l) {
+        bw.rec_off[l] = lo.rec_off[l];
+        bw.Nl[l] = lo.Nl[l];
+    }
+    return bw;
+}
+
+// next step after the one just run; false when the request is finished
+bool eng_advance(EngReq &r) {
+    const BatchProblem &pr = r.pr;
+    const int top = std::min(pr.l1, pr.lo.L + 1);  // backward levels below run one per step
+    switch (r.phase) {
+    case 0:
+        if (++r.level < pr.l0) return true;
+        r.phase = 1;
+        return true;
+    case 1:
+        if (pr.l1 <= pr.lo.L) { r.phase = 2; return true; }
+        r.phase = 3;
+        r.level = top - 1;
+        return true;
+    case 2:
+        if (top == 0) return false;
+        r.phase = 3;
+        r.level = top - 1;
+        return true;
+    default:
+        return --r.level >= 0;
+    }
+}
+
+ks_status status_of(unsigned f) {
+    return (f & ks::FLAG_NOT_SPD) ? KS_E_NOT_SPD
+         : (f & ks::FLAG_NONFINITE) ? KS_E_NONFINITE
+         : (f & ks::FLAG_RANK) ? KS_E_RANK : KS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ks_status ks_engine_create(void *workspace, size_t ws_bytes, void *hip_stream, ks_engine **out) {
+    if (!out) return KS_E_ARG;
+    *out = nullptr;
+    const size_t flags_bytes = align_up(sizeof(unsigned) * kEngSlots);
+    if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0 || ws_bytes < ((size_t)1 << 20))
+        return KS_E_WORKSPACE;
+    ks_engine *e = new (std::nothrow) ks_engine;
+    if (!e) return KS_E_ARG;
+    e->ws = static_cast<char *>(workspace);
+    e->stream = static_cast<hipStream_t>(hip_stream);
+    // 1/16 of the workspace (at least 256 KiB) for launch tables, the status
+    // words after them, the rest for request regions
+    size_t tab = std::max<size_t>((size_t)256 << 10, ws_bytes / 16) / kAlign * kAlign;
+    e->region_bytes = (ws_bytes - tab - flags_bytes) / kAlign * kAlign;
+    e->tab_off = e->region_bytes;
+    e->tab_bytes = tab;
+    e->dflags = reinterpret_cast<unsigned *>(e->ws + e->tab_off + tab);
+    e->free_list[0] = e->region_bytes;
+    for (int32_t s = 0; s < kEngSlots; ++s) e->free_slots.insert(s);
+    e->tab_used = kEngTabFixed;
+    e->next_ticket = 1;
+    e->ticks = 0;
+    e->tail_passes = 2;
+    if (const char *v = std::getenv("KS_TAIL_PASSES")) e->tail_passes = std::atoi(v);
+    e->switch_cols = 1024;
+    if (const char *v = std::getenv("KS_FP32_SWITCH")) e->switch_cols = std::atoll(v);
+    e->hflags.assign(kEngSlots, 0u);
+    *out = e;
+    return KS_OK;
+}
+
+ks_status ks_engine_submit(ks_engine *e, const ks_desc *desc, const ks_io *io, int32_t want_cov,
+                           uint64_t *ticket) {
+    if (!e || !desc || !io || !ticket || !valid_desc(desc)) return KS_E_ARG;
+    EngReq r{};
+    BatchProblem &pr = r.pr;
+    pr.d = *desc;
+    pr.kset = ks::find_kernels(desc->n, desc->m);
+    if (!pr.kset || !make_layout(desc, pr.kset, &pr.lo)) return KS_E_ARG;
+    if (!io->u_out || (want_cov && !io->cov_out)) return KS_E_ARG;
+    if (desc->k > 0 && (!io->F || !io->c || !io->K)) return KS_E_ARG;
+    if (desc->m > 0 && (!io->G || !io->o || !io->C)) return KS_E_ARG;
+    // schedule, exactly as a single plan (and a batch) derives it
+    pr.l_switch = 0;
+    if (desc->precision == KS_FP32_FORM)
+        while (pr.l_switch < pr.lo.L && pr.lo.Nl[pr.l_switch] > e->switch_cols) ++pr.l_switch;
+    int l0 = tail_start(pr.lo, pr.kset->upb_fwd_tail, e->tail_passes, false);
+    if (pr.l_switch > 0 && l0 <= pr.l_switch) l0 = pr.l_switch + 1;
+    pr.l0 = std::min(l0, pr.lo.L);
+    int l1 = tail_start(pr.lo, pr.kset->upb_bwd_tail[ks::BWD_BOTH], e->tail_passes, true);
+    pr.l1 = std::max(l1, pr.l_switch);
+    pr.rank_tol = 64.0 * (pr.l_switch > 0 ? 1.1920928955078125e-07 : 2.220446049250313e-16);
+    // bound on the request's share of one tick's tables
+    const int mode = want_cov ? ks::BWD_BOTH : ks::BWD_Y;
+    int64_t maxb = 1;
+    for (int l = 0; l < pr.l0; ++l) maxb = std::max(maxb, fwd_blocks(pr, l));
+    for (int l = 0; l < std::min(pr.l1, pr.lo.L + 1); ++l) maxb = std::max(maxb, bwd_blocks(pr, l, mode));
+    r.tab_need = std::max({sizeof(ks::FwdArgs), sizeof(ks::FwdTailArgs), sizeof(ks::BwdArgs)})
+               + (size_t)(maxb + 1) * (sizeof(int32_t) * 2 + sizeof(int64_t)) + sizeof(int32_t);
+    const size_t region = align_up(pr.lo.total);
+    if (region > e->region_bytes || kEngTabFixed + r.tab_need > e->tab_bytes) return KS_E_WORKSPACE;
+    if (e->free_slots.empty() || e->tab_used + r.tab_need > e->tab_bytes) return KS_E_BUSY;
+    size_t off;
+    if (!eng_alloc(e, region, &off)) return KS_E_BUSY;
+    pr.ws_off = off;
+    r.io = *io;
+    r.cov = want_cov != 0;
+    r.slot = *e->free_slots.begin();
+    e->free_slots.erase(e->free_slots.begin());
+    r.phase = pr.l0 > 0 ? 0 : 1;
+    r.level = 0;
+    r.fresh = true;
+    r.ticket = e->next_ticket++;
+    e->tab_used += r.tab_need;
+    *ticket = r.ticket;
+    e->inflight.push_back(r);
+    return KS_OK;
+}
+
+ks_status ks_engine_step(ks_engine *e, int32_t *finished) {
+    if (!e) return KS_E_ARG;
+    if (finished) *finished = 0;
+    if (e->inflight.empty()) return KS_OK;
+    const size_t R = e->inflight.size();
+    std::vector<ks::FwdArgs> ftab;
+    std::vector<ks::FwdTailArgs> ttab;
+    std::vector<ks::BwdArgs> btab;
+    std::vector<int32_t> item, level, clear, idx(R, -1);
+    std::vector<int64_t> blk;
+    std::vector<BLaunch> launches;
+    std::vector<const ks::KernelSet *> classes;
+    for (size_t q = 0; q < R; ++q) {
+        EngReq &r = e->inflight[q];
+        if (std::find(classes.begin(), classes.end(), r.pr.kset) == classes.end()) classes.push_back(r.pr.kset);
+        if (r.fresh) clear.push_back(r.slot);
+        if (r.phase == 0) { idx[q] = (int32_t)ftab.size(); ftab.push_back(eng_fwd_args(e, r, r.level)); }
+        else if (r.phase == 1) { idx[q] = (int32_t)ttab.size(); ttab.push_back(eng_tail_args(e, r)); }
+        else { idx[q] = (int32_t)btab.size(); btab.push_back(eng_bwd_args(e, r)); }
+    }
+    auto add = [&](int32_t it, int64_t b, int32_t lv) {
+        item.push_back(it);
+        blk.push_back(b);
+        level.push_back(lv);
+    };
+    // launch list; a request's fold follows its level's launch
+    for (auto *cls : classes) {
+        for (int raw = 1; raw >= 0; --raw)
+            for (int v = 0; v < 3; ++v) {
+                BLaunch fl{BLaunch::FWD, cls, v, raw == 1, (int64_t)item.size(), 0};
+                std::vector<size_t> folds;
+                for (size_t q = 0; q < R; ++q) {
+                    const EngReq &r = e->inflight[q];
+                    if (r.pr.kset != cls || r.phase != 0 || (r.level == 0) != (raw == 1)) continue;
+                    if (fwd_variant(r.pr, r.level) != v) continue;
+                    const int64_t nb = fwd_blocks(r.pr, r.level);
+                    for (int64_t k = 0; k < nb; ++k) add(idx[q], k, r.level);
+                    fl.blocks += nb;
+                    if (r.pr.lo.Nl[r.level] & 1) folds.push_back(q);
+                }
+                if (fl.blocks) launches.push_back(fl);
+                BLaunch fo{BLaunch::FOLD, cls, v, raw == 1, (int64_t)item.size(), (int64_t)folds.size()};
+                for (size_t q : folds) add(idx[q], 0, e->inflight[q].level);
+                if (fo.blocks) launches.push_back(fo);
+            }
+        for (int raw = 1; raw >= 0; --raw) {
+            BLaunch t{BLaunch::FTAIL, cls, 0, raw == 1, (int64_t)item.size(), 0};
+            for (size_t q = 0; q < R; ++q) {
+                const EngReq &r = e->inflight[q];
+                if (r.pr.kset != cls || r.phase != 1 || (r.pr.l0 == 0) != (raw == 1)) continue;
+                add(idx[q], 0, r.pr.l0);
+                t.blocks += 1;
+            }
+            if (t.blocks) launches.push_back(t);
+        }
+        for (int mode : {(int)ks::BWD_Y, (int)ks::BWD_BOTH}) {
+            BLaunch t{BLaunch::BTAIL, cls, mode, false, (int64_t)item.size(), 0};
+            for (size_t q = 0; q < R; ++q) {
+                const EngReq &r = e->inflight[q];
+                if (r.pr.kset != cls || r.phase != 2 || (r.cov ? ks::BWD_BOTH : ks::BWD_Y) != mode) continue;
+                add(idx[q], 0, r.pr.lo.L);
+                t.blocks += 1;
+            }
+            if (t.blocks) launches.push_back(t);
+            for (int tr = 0; tr < 2; ++tr) {
+                // variant = mode * 2 + record type
+                BLaunch bl{BLaunch::BWD, cls, mode * 2 + tr, false, (int64_t)item.size(), 0};
+                for (size_t q = 0; q < R; ++q) {
+                    const EngReq &r = e->inflight[q];
+                    if (r.pr.kset != cls || r.phase != 3 || (r.cov ? ks::BWD_BOTH : ks::BWD_Y) != mode) continue;
+                    if ((r.level < r.pr.l_switch ? 1 : 0) != tr) continue;
+                    const int64_t nb = bwd_blocks(r.pr, r.level, mode);
+                    for (int64_t k = 0; k < nb; ++k) add(idx[q], k, r.level);
+                    bl.blocks += nb;
+                }
+                if (bl.blocks) launches.push_back(bl);
+            }
+        }
+    }
+    // one upload: argument tables, block maps, status words to clear
+    size_t off = 0;
+    const size_t o_f = off; off += tab_bytes<ks::FwdArgs>(ftab.size());
+    const size_t o_t = off; off += tab_bytes<ks::FwdTailArgs>(ttab.size());
+    const size_t o_b = off; off += tab_bytes<ks::BwdArgs>(btab.size());
+    const size_t o_i = off; off += tab_bytes<int32_t>(item.size());
+    const size_t o_k = off; off += tab_bytes<int64_t>(blk.size());
+    const size_t o_l = off; off += tab_bytes<int32_t>(level.size());
+    const size_t o_c = off; off += tab_bytes<int32_t>(clear.size());
+    if (off > e->tab_bytes) return KS_E_WORKSPACE;  // excluded by admission
+    e->staging.resize(off);
+    char *st = e->staging.data();
+    auto put = [&](size_t o, const void *src, size_t bytes) { if (bytes) std::memcpy(st + o, src, bytes); };
+    put(o_f, ftab.data(), sizeof(ks::FwdArgs) * ftab.size());
+    put(o_t, ttab.data(), sizeof(ks::FwdTailArgs) * ttab.size());
+    put(o_b, btab.data(), sizeof(ks::BwdArgs) * btab.size());
+    put(o_i, item.data(), sizeof(int32_t) * item.size());
+    put(o_k, blk.data(), sizeof(int64_t) * blk.size());
+    put(o_l, level.data(), sizeof(int32_t) * level.size());
+    put(o_c, clear.data(), sizeof(int32_t) * clear.size());
+    char *dt = e->ws + e->tab_off;
+    if (hipMemcpyAsync(dt, st, off, hipMemcpyHostToDevice, e->stream) != hipSuccess) return KS_E_HIP;
+    if (!clear.empty())
+        ks::launch_clear_flags_list(e->dflags, reinterpret_cast<const int32_t *>(dt + o_c), (int32_t)clear.size(),
+                                    e->stream);
+    const ks::FwdArgs *ft = reinterpret_cast<const ks::FwdArgs *>(dt + o_f);
+    const ks::FwdTailArgs *tt = reinterpret_cast<const ks::FwdTailArgs *>(dt + o_t);
+    const ks::BwdArgs *bt = reinterpret_cast<const ks::BwdArgs *>(dt + o_b);
+    const int32_t *mi = reinterpret_cast<const int32_t *>(dt + o_i);
+    const int64_t *mb = reinterpret_cast<const int64_t *>(dt + o_k);
+    const int32_t *ml = reinterpret_cast<const int32_t *>(dt + o_l);
+    for (const BLaunch &L : launches) {
+        const ks::BlockMap bm{mi + L.map0, mb + L.map0, ml + L.map0};
+        switch (L.kind) {
+        case BLaunch::FWD:
+            if (L.raw) L.kset->fwd_raw_b[L.variant == ks::FV_F32](ft, bm, L.blocks, e->stream);
+            else L.kset->fwd_b[L.variant](ft, bm, L.blocks, e->stream);
+            break;
+        case BLaunch::FOLD:
+            if (L.raw) L.kset->fold_raw_b[L.variant == ks::FV_F32](ft, bm, L.blocks, e->stream);
+            else L.kset->fold_b[L.variant](ft, bm, L.blocks, e->stream);
+            break;
+        case BLaunch::FTAIL:
+            (L.raw ? L.kset->fwd_tail_raw_b : L.kset->fwd_tail_b)(tt, bm, L.blocks, e->stream);
+            break;
+        case BLaunch::BTAIL:
+            L.kset->bwd_tail_b[L.variant](bt, bm, L.blocks, e->stream);
+            break;
+        case BLaunch::BWD:
+            L.kset->bwd_b[L.variant / 2][L.variant % 2](bt, bm, L.blocks, e->stream);
+            break;
+        }
+    }
+    if (hipGetLastError() != hipSuccess) return KS_E_HIP;
+    // advance; read the status words of the requests that finish
+    std::vector<char> fin(R, 0);
+    int32_t hi = -1;
+    for (size_t q = 0; q < R; ++q) {
+        EngReq &r = e->inflight[q];
+        r.fresh = false;
+        if (!eng_advance(r)) {
+            fin[q] = 1;
+            hi = std::max(hi, r.slot);
+        }
+    }
+    if (hi >= 0 && hipMemcpyAsync(e->hflags.data(), e->dflags, sizeof(unsigned) * (hi + 1), hipMemcpyDeviceToHost,
+                                  e->stream) != hipSuccess)
+        return KS_E_HIP;
+    if (hipStreamSynchronize(e->stream) != hipSuccess) return KS_E_HIP;
+    ++e->ticks;
+    std::vector<EngReq> keep;
+    keep.reserve(R);
+    int32_t nfin = 0;
+    for (size_t q = 0; q < R; ++q) {
+        EngReq &r = e->inflight[q];
+        if (!fin[q]) {
+            keep.push_back(r);
+            continue;
+        }
+        e->retired.emplace_back(r.ticket, status_of(e->hflags[r.slot]));
+        eng_free(e, r.pr.ws_off, align_up(r.pr.lo.total));
+        e->free_slots.insert(r.slot);
+        e->tab_used -= r.tab_need;
+        ++nfin;
+    }
+    e->inflight.swap(keep);
+    if (finished) *finished = nfin;
+    return KS_OK;
+}
+
+ks_status ks_engine_retired(ks_engine *e, int32_t capacity, uint64_t *tickets, ks_status *statuses,
+                            int32_t *count) {
+    if (!e || !count || capacity < 0 || (capacity > 0 && (!tickets || !statuses))) return KS_E_ARG;
+    const int32_t c = (int32_t)std::min<size_t>((size_t)capacity, e->retired.size());
+    for (int32_t i = 0; i < c; ++i) {
+        tickets[i] = e->retired[i].first;
+        statuses[i] = e->retired[i].second;
+    }
+    e->retired.erase(e->retired.begin(), e->retired.begin() + c);
+    *count = c;
+    return KS_OK;
+}
+
+ks_status ks_engine_query(const ks_engine *e, ks_engine_stats *out) {
+    if (!e || !out) return KS_E_ARG;
+    std::memset(out, 0, sizeof(*out));
+    out->inflight = (int64_t)e->inflight.size();
+    out->retired_pending = (int64_t)e->retired.size();
+    out->ticks = (int64_t)e->ticks;
+    out->region_bytes = e->region_bytes;
+    for (auto &f : e->free_list) {
+        out->free_bytes += f.second;
+        out->largest_free = std::max(out->largest_free, f.second);
+    }
+    return KS_OK;
+}
+
+ks_status ks_engine_destroy(ks_engine *e) {
+    if (!e) return KS_E_ARG;
+    delete e;
     return KS_OK;
 }
 

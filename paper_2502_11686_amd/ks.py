@@ -18,14 +18,15 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libks.so")
 
 KS_OK, KS_E_ARG, KS_E_WORKSPACE, KS_E_NOT_SPD, KS_E_RANK = 0, -1, -2, -3, -4
-KS_E_NONFINITE, KS_E_HIP, KS_E_ORDER = -5, -6, -7
+KS_E_NONFINITE, KS_E_HIP, KS_E_ORDER, KS_E_BUSY = -5, -6, -7, -8
 KS_FP64, KS_FP32_FORM = 0, 1
 KS_COV_DENSE, KS_COV_DIAG = 0, 1
 
 SYMBOLS = ("ks_workspace_bytes", "ks_supported", "ks_create", "ks_smooth", "ks_covariances",
            "ks_smooth_cov", "ks_destroy", "ks_status_string", "ks_plan_layout",
            "ks_time_kernels", "ks_kernel_time", "ks_batch_workspace_bytes", "ks_batch_create",
-           "ks_batch_smooth", "ks_batch_destroy")
+           "ks_batch_smooth", "ks_batch_destroy", "ks_engine_create", "ks_engine_submit",
+           "ks_engine_step", "ks_engine_retired", "ks_engine_query", "ks_engine_destroy")
 KS_TIME_OFF, KS_TIME_FWD_LEVEL0, KS_TIME_BWD_LEVEL0, KS_TIME_FWD_ALL, KS_TIME_BWD_ALL = range(5)
 
 
@@ -43,6 +44,12 @@ class Layout(ctypes.Structure):
 
 class Io(ctypes.Structure):
     _fields_ = [(f, ctypes.c_void_p) for f in ("H", "F", "c", "K", "G", "o", "C", "u_out", "cov_out")]
+
+
+class EngineStats(ctypes.Structure):
+    _fields_ = [("inflight", ctypes.c_int64), ("retired_pending", ctypes.c_int64), ("ticks", ctypes.c_int64),
+                ("region_bytes", ctypes.c_size_t), ("free_bytes", ctypes.c_size_t),
+                ("largest_free", ctypes.c_size_t)]
 
 
 class KsError(RuntimeError):
@@ -96,6 +103,20 @@ def lib():
     L.ks_batch_smooth.argtypes = [vp, ctypes.POINTER(Io), ctypes.c_int32, ctypes.POINTER(ctypes.c_int)]
     L.ks_batch_destroy.restype = ctypes.c_int
     L.ks_batch_destroy.argtypes = [vp]
+    L.ks_engine_create.restype = ctypes.c_int
+    L.ks_engine_create.argtypes = [vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+    L.ks_engine_submit.restype = ctypes.c_int
+    L.ks_engine_submit.argtypes = [vp, ctypes.POINTER(Desc), ctypes.POINTER(Io), ctypes.c_int32,
+                                   ctypes.POINTER(ctypes.c_uint64)]
+    L.ks_engine_step.restype = ctypes.c_int
+    L.ks_engine_step.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    L.ks_engine_retired.restype = ctypes.c_int
+    L.ks_engine_retired.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64),
+                                    ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int32)]
+    L.ks_engine_query.restype = ctypes.c_int
+    L.ks_engine_query.argtypes = [vp, ctypes.POINTER(EngineStats)]
+    L.ks_engine_destroy.restype = ctypes.c_int
+    L.ks_engine_destroy.argtypes = [vp]
     _lib = L
     return L
 
@@ -134,6 +155,33 @@ def _check(t: Optional[torch.Tensor], name: str, shape, device, allow_none=False
         raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
 
 
+def _device(device) -> torch.device:
+    """A CUDA/HIP device with its index (``"cuda"`` means the current one)."""
+    d = torch.device(device) if device is not None else torch.device("cuda")
+    if d.type != "cuda":
+        raise ValueError(f"libks runs on GPU devices only, got {d}")
+    return d if d.index is not None else torch.device("cuda", torch.cuda.current_device())
+
+
+def _make_io(shape, args, u, cov, device) -> Io:
+    """Check one problem's device tensors against its shape
+    (k, n, m, K_diag, C_diag, fp32) and return their pointers."""
+    k, n, m, kd, cd = shape[:5]
+    H, F, c, K, G, o, C = args
+    _check(H, "H", (k, n, n), device, allow_none=True)
+    _check(F, "F", (k, n, n), device)
+    _check(c, "c", (k, n), device)
+    _check(K, "K", (k, n) if kd else (k, n, n), device)
+    _check(G, "G", (k + 1, m, n), device)
+    _check(o, "o", (k + 1, m), device)
+    _check(C, "C", (k + 1, m) if cd else (k + 1, m, m), device)
+    _check(u, "u_out", (k + 1, n), device)
+    if cov is not None:
+        _check(cov, "cov_out", (k + 1, n, n), device)
+    return Io(*[None if t is None else t.data_ptr() for t in (H, F, c, K, G, o, C)],
+              u.data_ptr(), None if cov is None else cov.data_ptr())
+
+
 class Plan:
     """A smoothing plan for one problem shape, owning its device workspace."""
 
@@ -143,7 +191,7 @@ class Plan:
         self.k, self.n, self.m = int(k), int(n), int(m)
         self.K_diag, self.C_diag = bool(K_diag), bool(C_diag)
         self.fp32 = bool(fp32)
-        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.device = _device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self._desc = make_desc(k, n, m, K_diag, C_diag, fp32)
         L = lib()
@@ -279,7 +327,7 @@ class Batch:
     def __init__(self, shapes, device=None, stream=None):
         self.shapes = [tuple(sh) for sh in shapes]
         self.count = len(self.shapes)
-        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        self.device = _device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         descs = (Desc * self.count)(*[make_desc(k, n, m, kd, cd, f32) for (k, n, m, kd, cd, f32) in self.shapes])
         self._descs = descs
@@ -308,20 +356,8 @@ class Batch:
         covs[i]); returns the per-problem status list."""
         want_cov = covs is not None and all(c is not None for c in covs)
         io = (Io * self.count)()
-        for i, ((k, n, m, kd, cd, _f), args) in enumerate(zip(self.shapes, inputs)):
-            H, F, c, K, G, o, C = args
-            _check(H, "H", (k, n, n), self.device, allow_none=True)
-            _check(F, "F", (k, n, n), self.device)
-            _check(c, "c", (k, n), self.device)
-            _check(K, "K", (k, n) if kd else (k, n, n), self.device)
-            _check(G, "G", (k + 1, m, n), self.device)
-            _check(o, "o", (k + 1, m), self.device)
-            _check(C, "C", (k + 1, m) if cd else (k + 1, m, m), self.device)
-            _check(us[i], "u_out", (k + 1, n), self.device)
-            if want_cov:
-                _check(covs[i], "cov_out", (k + 1, n, n), self.device)
-            io[i] = Io(*[None if t is None else t.data_ptr() for t in (H, F, c, K, G, o, C)],
-                       us[i].data_ptr(), covs[i].data_ptr() if want_cov else None)
+        for i, (shape, args) in enumerate(zip(self.shapes, inputs)):
+            io[i] = _make_io(shape, args, us[i], covs[i] if want_cov else None, self.device)
         st = (ctypes.c_int * self.count)()
         r = lib().ks_batch_smooth(self._h, io, 1 if want_cov else 0, st)
         statuses = list(st)
@@ -333,6 +369,87 @@ class Batch:
         if getattr(self, "_h", None) is not None:
             lib().ks_batch_destroy(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Engine:
+    """Continuous batching of requests over one device workspace (see
+    include/ks.h): ``submit`` admits a request if its region fits now,
+    ``step`` advances every in-flight request by one step of its schedule and
+    returns the (ticket, status) pairs of the requests that finished."""
+
+    def __init__(self, ws_bytes: int, device=None, stream=None):
+        self.device = _device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.workspace = torch.empty(int(ws_bytes) + 256, dtype=torch.uint8, device=self.device)
+        ptr = (self.workspace.data_ptr() + 255) // 256 * 256
+        h = ctypes.c_void_p()
+        st = lib().ks_engine_create(ctypes.c_void_p(ptr), int(ws_bytes), ctypes.c_void_p(self.stream.cuda_stream),
+                                    ctypes.byref(h))
+        if st != KS_OK:
+            raise KsError(st, "ks_engine_create")
+        self._h = h
+        self._live = {}   # ticket -> tensors the request reads or writes
+
+    @staticmethod
+    def footprint(shape) -> int:
+        """Device bytes a request of shape (k, n, m, K_diag, C_diag, fp32) holds
+        while in flight (0 if unsupported)."""
+        d = make_desc(*shape)
+        return (int(lib().ks_workspace_bytes(ctypes.byref(d))) + 255) // 256 * 256
+
+    def submit(self, shape, inputs, u, cov=None) -> Optional[int]:
+        """Admit a request; returns its ticket, or None when it does not fit
+        now (retry after a step).  The tensors are held until it retires."""
+        d = make_desc(*shape)
+        io = _make_io(shape, inputs, u, cov, self.device)
+        t = ctypes.c_uint64()
+        st = lib().ks_engine_submit(self._h, ctypes.byref(d), ctypes.byref(io), 0 if cov is None else 1,
+                                    ctypes.byref(t))
+        if st == KS_E_BUSY:
+            return None
+        if st != KS_OK:
+            raise KsError(st, "ks_engine_submit")
+        self._live[t.value] = (inputs, u, cov)
+        return t.value
+
+    def step(self):
+        fin = ctypes.c_int32()
+        st = lib().ks_engine_step(self._h, ctypes.byref(fin))
+        if st != KS_OK:
+            raise KsError(st, "ks_engine_step")
+        out = []
+        cap = max(int(fin.value), 1)
+        tickets = (ctypes.c_uint64 * cap)()
+        statuses = (ctypes.c_int * cap)()
+        while True:
+            cnt = ctypes.c_int32()
+            st = lib().ks_engine_retired(self._h, cap, tickets, statuses, ctypes.byref(cnt))
+            if st != KS_OK:
+                raise KsError(st, "ks_engine_retired")
+            for i in range(cnt.value):
+                self._live.pop(tickets[i], None)
+                out.append((int(tickets[i]), int(statuses[i])))
+            if cnt.value < cap:
+                return out
+
+    def stats(self) -> dict:
+        s = EngineStats()
+        st = lib().ks_engine_query(self._h, ctypes.byref(s))
+        if st != KS_OK:
+            raise KsError(st, "ks_engine_query")
+        return {f: getattr(s, f) for f, _t in EngineStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            lib().ks_engine_destroy(self._h)
+            self._h = None
+            self._live.clear()
 
     def __del__(self):
         try:

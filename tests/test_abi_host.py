@@ -28,7 +28,7 @@ def test_exports_every_declared_symbol():
 
 def test_status_strings():
     L = ks.lib()
-    for st in range(-7, 1):
+    for st in range(-8, 1):
         assert L.ks_status_string(st)
 
 
@@ -80,3 +80,68 @@ def test_argument_errors():
     assert L.ks_create(ctypes.byref(d), ctypes.c_void_p(1 << 20), nb - 256, None, ctypes.byref(h)) == ks.KS_E_WORKSPACE
     assert L.ks_covariances(None, None) == ks.KS_E_ARG
     assert L.ks_destroy(None) == ks.KS_E_ARG
+
+
+def _fake_io(with_cov=True):
+    # distinct non-null addresses; submit is host-only and never dereferences them
+    return ks.Io(*[ctypes.c_void_p(0x10000 * (i + 1)) for i in range(8)],
+                 ctypes.c_void_p(0x100000) if with_cov else None)
+
+
+def test_engine_admission_is_exact_footprint_first_fit():
+    """Admission by device footprint: each request holds exactly its single-plan
+    workspace (rounded to 256 B); requests that do not fit now are refused with
+    KS_E_BUSY, ones that can never fit with KS_E_WORKSPACE; submit launches
+    nothing (host-only)."""
+    L = ks.lib()
+    ws = 64 << 20
+    h = ctypes.c_void_p()
+    assert L.ks_engine_create(ctypes.c_void_p(1 << 30), ws, None, ctypes.byref(h)) == ks.KS_OK
+    st = ks.EngineStats()
+    assert L.ks_engine_query(h, ctypes.byref(st)) == ks.KS_OK
+    region = st.region_bytes
+    assert st.free_bytes == region == st.largest_free and region <= ws - ws // 16
+    shape = (20000, 6, 3, False, False, False)
+    fp = ks.Engine.footprint(shape)
+    assert fp == (ks.workspace_bytes(*shape) + 255) // 256 * 256
+    d = ks.make_desc(*shape)
+    io = _fake_io()
+    tickets = []
+    while True:
+        t = ctypes.c_uint64()
+        r = L.ks_engine_submit(h, ctypes.byref(d), ctypes.byref(io), 1, ctypes.byref(t))
+        if r == ks.KS_E_BUSY:
+            break
+        assert r == ks.KS_OK
+        tickets.append(t.value)
+    assert len(tickets) == region // fp
+    assert tickets == list(range(1, len(tickets) + 1))
+    assert L.ks_engine_query(h, ctypes.byref(st)) == ks.KS_OK
+    assert st.inflight == len(tickets) and st.free_bytes == region - len(tickets) * fp
+    # a smaller request still fits in what is left
+    small = (100, 6, 3, False, False, False)
+    if region - len(tickets) * fp >= ks.Engine.footprint(small):
+        t = ctypes.c_uint64()
+        ds = ks.make_desc(*small)
+        assert L.ks_engine_submit(h, ctypes.byref(ds), ctypes.byref(io), 1, ctypes.byref(t)) == ks.KS_OK
+    # never fits
+    big = ks.make_desc(10_000_000, 6, 3, False, False)
+    t = ctypes.c_uint64()
+    assert L.ks_engine_submit(h, ctypes.byref(big), ctypes.byref(io), 1, ctypes.byref(t)) == ks.KS_E_WORKSPACE
+    # argument errors
+    bad = ks.make_desc(100, 7, 3, False, False)
+    assert L.ks_engine_submit(h, ctypes.byref(bad), ctypes.byref(io), 1, ctypes.byref(t)) == ks.KS_E_ARG
+    nocov = _fake_io(with_cov=False)
+    assert L.ks_engine_submit(h, ctypes.byref(d), ctypes.byref(nocov), 1, ctypes.byref(t)) == ks.KS_E_ARG
+    cnt = ctypes.c_int32()
+    assert L.ks_engine_retired(h, 0, None, None, ctypes.byref(cnt)) == ks.KS_OK and cnt.value == 0
+    assert L.ks_engine_destroy(h) == ks.KS_OK
+
+
+def test_engine_create_errors():
+    L = ks.lib()
+    h = ctypes.c_void_p()
+    assert L.ks_engine_create(None, 64 << 20, None, ctypes.byref(h)) == ks.KS_E_WORKSPACE
+    assert L.ks_engine_create(ctypes.c_void_p((1 << 30) + 8), 64 << 20, None, ctypes.byref(h)) == ks.KS_E_WORKSPACE
+    assert L.ks_engine_create(ctypes.c_void_p(1 << 30), 1000, None, ctypes.byref(h)) == ks.KS_E_WORKSPACE
+    assert L.ks_engine_create(ctypes.c_void_p(1 << 30), 64 << 20, None, None) == ks.KS_E_ARG

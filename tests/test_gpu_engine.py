@@ -1,0 +1,136 @@
+"""GPU: the continuous-batching engine.
+
+Requests arrive between ticks, are admitted by device footprint, and advance
+one schedule step per tick in launches shared with every other in-flight
+request.  Each request's result must equal, bitwise, the same problem
+smoothed alone by a single plan, and hence the oracle; statuses are per
+request; a workspace too small for everything at once queues requests
+(KS_E_BUSY) without changing any result."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import seq
+from paper_2502_11686_amd import gen, ks
+
+pytestmark = pytest.mark.gpu
+
+
+def requests(seed=11, count=14):
+    rng = np.random.default_rng(seed)
+    shapes = [(2, 1), (4, 2), (6, 3), (8, 4), (12, 6), (16, 8), (24, 12), (32, 16), (6, 3), (1, 1), (3, 2),
+              (5, 2), (6, 6), (48, 24)]
+    out = []
+    for i in range(count):
+        n, m = shapes[i % len(shapes)]
+        k = int(rng.integers(0 if m >= n else 1, 3000 if n <= 16 else 300))
+        cov = "dense" if i % 2 else "diag"
+        p = gen.make_problem(np.random.default_rng(seed * 100 + i), k, n, m, cov=cov)
+        out.append(dict(p=p, fp32=bool(i % 3 == 1), cov=bool(i % 4 != 3), arrive=int(rng.integers(0, 12))))
+    return out
+
+
+def alone(p, fp32, want_cov):
+    u, S = ks.smooth_problem(p, want_cov=want_cov, fp32=fp32)
+    torch.cuda.synchronize()
+    return u.cpu().numpy(), None if S is None else S.cpu().numpy()
+
+
+def serve(reqs, ws_bytes):
+    """Tick loop: submit the requests whose arrival tick has come (queued ones
+    retry every tick), step, collect.  Returns per request (u, S, status,
+    ticks in flight) and the number of refusals."""
+    eng = ks.Engine(ws_bytes)
+    outs, tick_of, done, refused = {}, {}, {}, 0
+    pending = list(range(len(reqs)))
+    tick = 0
+    while pending or eng.stats()["inflight"]:
+        still = []
+        for i in pending:
+            r = reqs[i]
+            if r["arrive"] > tick:
+                still.append(i)
+                continue
+            p = r["p"]
+            u = torch.empty((p.k + 1, p.n), dtype=torch.float64, device="cuda")
+            S = torch.empty((p.k + 1, p.n, p.n), dtype=torch.float64, device="cuda") if r["cov"] else None
+            shape = (p.k, p.n, p.m, p.K_diag, p.C_diag, r["fp32"])
+            t = eng.submit(shape, ks.to_device(p), u, S)
+            if t is None:
+                refused += 1
+                still.append(i)
+                continue
+            outs[t] = (i, u, S)
+            tick_of[t] = tick
+        pending = still
+        for t, st in eng.step():
+            i, u, S = outs.pop(t)
+            done[i] = (u.cpu().numpy(), None if S is None else S.cpu().numpy(), st, tick - tick_of[t] + 1)
+        tick += 1
+        assert tick < 10000
+    assert not outs
+    stats = eng.stats()
+    assert stats["free_bytes"] == stats["region_bytes"]
+    eng.close()
+    return done, refused
+
+
+def check_against_alone(reqs, done):
+    for i, r in enumerate(reqs):
+        u, S, st, _ = done[i]
+        assert st == ks.KS_OK, (i, st)
+        ua, Sa = alone(r["p"], r["fp32"], r["cov"])
+        assert np.array_equal(u, ua), (i, r["p"].n, r["p"].k, r["fp32"])
+        if r["cov"]:
+            assert np.array_equal(S, Sa), (i, r["p"].n, r["p"].k, r["fp32"])
+
+
+def test_engine_mixed_arrivals_equal_alone_and_oracle():
+    reqs = requests()
+    done, _ = serve(reqs, 256 << 20)
+    check_against_alone(reqs, done)
+    for i, r in enumerate(reqs):
+        if r["fp32"]:
+            continue
+        ref = seq.smooth(r["p"])
+        u = done[i][0]
+        eu = np.max(np.abs(u - ref["u"])) / np.max(np.abs(ref["u"]))
+        assert eu < 1e-10, (i, eu)
+        if r["cov"]:
+            S = done[i][1]
+            es = np.max(np.linalg.norm(S - ref["cov"], axis=(1, 2)) / np.linalg.norm(ref["cov"], axis=(1, 2)))
+            assert es < 1e-9, (i, es)
+
+
+def test_engine_admission_under_pressure():
+    """A workspace that holds only a few requests at once: the rest are
+    refused, queued and admitted as regions free up; results unchanged."""
+    reqs = requests(seed=13, count=10)
+    need = max(ks.Engine.footprint((r["p"].k, r["p"].n, r["p"].m, r["p"].K_diag, r["p"].C_diag, r["fp32"]))
+               for r in reqs)
+    ws = max(2 * need, 1 << 20) * 16 // 15 + (1 << 16)
+    done, refused = serve(reqs, ws)
+    assert refused > 0
+    check_against_alone(reqs, done)
+
+
+def test_engine_statuses_per_request():
+    reqs = requests(seed=17, count=6)
+    bad = gen.make_problem(np.random.default_rng(3), 40, 2, 1)
+    bad.G[:] = 0.0
+    reqs.append(dict(p=bad, fp32=False, cov=True, arrive=2))
+    eng = ks.Engine(128 << 20)
+    keep, status = {}, {}
+    for i, r in enumerate(reqs):
+        p = r["p"]
+        u = torch.empty((p.k + 1, p.n), dtype=torch.float64, device="cuda")
+        S = torch.empty((p.k + 1, p.n, p.n), dtype=torch.float64, device="cuda") if r["cov"] else None
+        t = eng.submit((p.k, p.n, p.m, p.K_diag, p.C_diag, r["fp32"]), ks.to_device(p), u, S)
+        assert t is not None
+        keep[t] = i
+    while eng.stats()["inflight"]:
+        for t, st in eng.step():
+            status[keep[t]] = st
+    eng.close()
+    assert [status[i] for i in range(len(reqs) - 1)] == [ks.KS_OK] * (len(reqs) - 1)
+    assert status[len(reqs) - 1] == ks.KS_E_RANK
