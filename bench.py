@@ -93,8 +93,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", type=int, default=1, choices=(0, 1, 2, 3))
+    ap.add_argument("--workload", type=int, default=1, choices=(0, 1, 2, 3, 4))
     ap.add_argument("--problems", type=int, default=512, help="batched workload: number of problems")
+    ap.add_argument("--requests", type=int, default=48, help="serving workload: number of requests")
+    ap.add_argument("--rate", type=float, default=100.0, help="serving workload: Poisson arrival rate (1/s)")
+    ap.add_argument("--hbm-gb", type=float, default=96.0,
+                    help="serving workload: engine workspace (request regions) in GB; inputs and outputs "
+                         "are admitted against the same amount again")
     ap.add_argument("--k", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
@@ -111,6 +116,8 @@ def main():
 
     if args.workload == 3:
         return batch_bench(args)
+    if args.workload == 4:
+        return serve_bench(args)
     p = gen.workload(args.workload, k=args.k)
     dev = torch.device("cuda", 0)
     tens = ks.to_device(p, dev)
@@ -281,6 +288,148 @@ def batch_bench(args):
         "err_vs_oracle": out["fp64"]["err_vs_oracle"], "fp32_form": out["fp32_form"],
         "roofline": None,
     }
+    print(json.dumps(line), flush=True)
+
+
+def _make_request(req):
+    from paper_2502_11686_amd import gen
+    p = gen.request_problem(req)
+    return p
+
+
+def serve_bench(args):
+    """Serving: Poisson arrivals of requests (k log-uniform in [100, 2e5],
+    n in {6, 12, 24}, m = n/2, per-step F, dense K and C, half of them in the
+    FP32 form) into the continuous-batching engine.  A request's latency runs
+    from its arrival to its outputs being final, including the copy of its
+    inputs from pinned host memory; value = smoothed states of all requests
+    per second of makespan (first arrival to last retirement)."""
+    import numpy as np
+    import torch
+    from concurrent.futures import ProcessPoolExecutor
+
+    from paper_2502_11686_amd import gen, ks
+
+    dev = torch.device("cuda", 0)
+    reqs = gen.serving_requests(args.requests, args.rate)
+    t_gen = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
+        probs = list(ex.map(_make_request, reqs))
+    host = []
+    for p in probs:
+        arrs = [None if a is None else torch.from_numpy(np.ascontiguousarray(a)).pin_memory()
+                for a in (p.H, p.F, p.c, p.K, p.G, p.o, p.C)]
+        host.append(arrs)
+    t_gen = time.perf_counter() - t_gen
+    print(f"serving: {len(reqs)} requests generated in {t_gen:.1f} s", file=sys.stderr, flush=True)
+
+    ws = int(args.hbm_gb * 1e9) // 256 * 256
+    io_budget = ws
+    eng = ks.Engine(ws, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def io_bytes(p):
+        per = sum(0 if a is None else a.nbytes for a in (p.H, p.F, p.c, p.K, p.G, p.o, p.C))
+        return per + 8 * (p.k + 1) * p.n * (p.n + 1)
+
+    # warm-up: one small request of each (n, form) through the engine
+    for n in (6, 12, 24):
+        for f32 in (False, True):
+            wp = gen.make_problem(np.random.default_rng(n), 300, n, n // 2, cov="dense")
+            u = torch.empty((wp.k + 1, n), dtype=torch.float64, device=dev)
+            S = torch.empty((wp.k + 1, n, n), dtype=torch.float64, device=dev)
+            eng.submit((wp.k, n, n // 2, False, False, f32), ks.to_device(wp, dev), u, S)
+    while eng.stats()["inflight"]:
+        eng.step()
+    torch.cuda.synchronize()
+
+    queue, nxt = [], 0
+    inflight, lat, io_used = {}, {}, 0
+    results = {}
+    ticks = 0
+    t0 = time.perf_counter()
+    while nxt < len(reqs) or queue or inflight:
+        now = time.perf_counter() - t0
+        while nxt < len(reqs) and reqs[nxt]["arrival_s"] <= now:
+            queue.append(nxt)
+            nxt += 1
+        # FIFO admission: stop at the first request that does not fit
+        while queue:
+            i = queue[0]
+            p, r = probs[i], reqs[i]
+            need = io_bytes(p)
+            if io_used + need > io_budget:
+                break
+            dargs = tuple(None if a is None else a.to(dev, non_blocking=True) for a in host[i])
+            u = torch.empty((p.k + 1, p.n), dtype=torch.float64, device=dev)
+            S = torch.empty((p.k + 1, p.n, p.n), dtype=torch.float64, device=dev)
+            t = eng.submit((p.k, p.n, p.m, p.K_diag, p.C_diag, r["fp32"]), dargs, u, S)
+            if t is None:
+                break
+            queue.pop(0)
+            io_used += need
+            inflight[t] = (i, u, S, need)
+        if not inflight:
+            if queue:
+                raise RuntimeError(f"request {queue[0]} does not fit the HBM budget")
+            if nxt < len(reqs):
+                time.sleep(max(0.0, reqs[nxt]["arrival_s"] - (time.perf_counter() - t0)))
+            continue
+        for t, st in eng.step():
+            i, u, S, need = inflight.pop(t)
+            lat[i] = time.perf_counter() - t0 - reqs[i]["arrival_s"]
+            io_used -= need
+            results[i] = (st, u, S)
+        ticks += 1
+    stream.synchronize()
+    makespan = time.perf_counter() - t0 - reqs[0]["arrival_s"]
+    steps_total = sum(p.k + 1 for p in probs)
+    bad = [i for i, (st, _u, _S) in results.items() if st != ks.KS_OK]
+    lat_ms = np.array([lat[i] for i in range(len(reqs))]) * 1e3
+    by_form = {}
+    for name, f in (("fp64", False), ("fp32_form", True)):
+        idx = [i for i, r in enumerate(reqs) if r["fp32"] == f]
+        if idx:
+            by_form[name] = dict(requests=len(idx), p50_ms=float(np.percentile(lat_ms[idx], 50)),
+                                 p99_ms=float(np.percentile(lat_ms[idx], 99)),
+                                 states=int(sum(probs[i].k + 1 for i in idx)))
+    err = None
+    if not args.no_check:
+        from oracle import seq
+        # the three shortest requests of each form, plus the shortest FP32-form
+        # request long enough to run FP32 levels (more than 1024 columns at level 0)
+        order = sorted(range(len(reqs)), key=lambda i: probs[i].k)
+        check = [i for i in order if not reqs[i]["fp32"]][:3] + [i for i in order if reqs[i]["fp32"]][:3]
+        check += [i for i in order if reqs[i]["fp32"] and probs[i].k >= 4096][:1]
+        err = {}
+        for name, f in (("fp64", False), ("fp32_form", True)):
+            eu = es = 0.0
+            cnt = 0
+            for i in check:
+                if reqs[i]["fp32"] != f:
+                    continue
+                ref = seq.smooth(probs[i])
+                _st, u, S = results[i]
+                u, S = u.cpu().numpy(), S.cpu().numpy()
+                eu = max(eu, float(np.max(np.abs(u - ref["u"])) / np.max(np.abs(ref["u"]))))
+                es = max(es, float(np.max(np.linalg.norm(S - ref["cov"], axis=(1, 2)) /
+                                          np.linalg.norm(ref["cov"], axis=(1, 2)))))
+                cnt += 1
+            err[name] = dict(state=eu, cov=es, requests_checked=cnt)
+    line = {
+        "metric": "smoothed time steps/s incl. covariances, FP64 vs FP32 form; p50/p99 latency",
+        "value": steps_total / makespan, "unit": "steps/s", "n_gpus": 1, "steps": len(reqs),
+        "warmup": 6, "ms_per_step": makespan * 1e3 / len(reqs), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32",
+        "data": "synthetic (seeded generator; per-step F and G, dense K and C, Poisson arrivals)",
+        "config": {"workload": f"serving: {len(reqs)} requests, Poisson {args.rate:g}/s, k log-uniform "
+                               "[100,200000], n in {6,12,24}, m=n/2, half FP32 form, continuous batching",
+                   "requests": len(reqs), "states": steps_total, "hbm_budget_gb": args.hbm_gb},
+        "p50_ms": float(np.percentile(lat_ms, 50)), "p99_ms": float(np.percentile(lat_ms, 99)),
+        "by_form": by_form, "ticks": ticks, "failed_requests": len(bad), "err_vs_oracle": err,
+        "roofline": None,
+    }
+    eng.close()
     print(json.dumps(line), flush=True)
 
 

@@ -256,6 +256,11 @@ ks_status ks_engine_step(ks_engine *engine, int32_t *finished);
 ks_status ks_engine_retired(ks_engine *engine, int32_t capacity, uint64_t *tickets,
                             ks_status *statuses, int32_t *count);
 
+/* The status of one request: KS_OK with *result set once it has finished
+ * (it is then removed from the retired list), KS_E_BUSY while it is in
+ * flight, KS_E_ARG for a ticket that is neither (unknown or collected). */
+ks_status ks_engine_poll(ks_engine *engine, uint64_t ticket, ks_status *result);
+
 ks_status ks_engine_query(const ks_engine *engine, ks_engine_stats *out);
 
 /* Frees host state only; requests still in flight are abandoned (no kernels

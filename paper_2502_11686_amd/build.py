@@ -33,16 +33,29 @@ def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip"))) + [os.path.join(CSRC, "ks_runtime.cpp")]
 
 
-def _headers_mtime():
-    hs = glob.glob(os.path.join(CSRC, "*.h")) + glob.glob(os.path.join(INCLUDE, "*.h"))
-    return max(os.path.getmtime(h) for h in hs)
+def _deps(src: str, seen=None) -> set:
+    """Project headers src includes, transitively (quoted includes only)."""
+    seen = set() if seen is None else seen
+    for line in open(src):
+        line = line.strip()
+        if not line.startswith("#include \""):
+            continue
+        name = line.split('"')[1]
+        for d in (os.path.dirname(src), CSRC, INCLUDE):
+            h = os.path.join(d, name)
+            if os.path.exists(h):
+                if h not in seen:
+                    seen.add(h)
+                    _deps(h, seen)
+                break
+    return seen
 
 
 def _compile(src: str, force: bool) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     if not force and os.path.exists(obj):
         t = os.path.getmtime(obj)
-        if t >= os.path.getmtime(src) and t >= _headers_mtime():
+        if all(t >= os.path.getmtime(f) for f in (src, *_deps(src))):
             return obj
     cmd = [HIPCC, *FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", src, "-o", obj + ".tmp"]
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -1337,6 +1337,19 @@ ks_status ks_engine_retired(ks_engine *e, int32_t capacity, uint64_t *tickets, k
     return KS_OK;
 }
 
+ks_status ks_engine_poll(ks_engine *e, uint64_t ticket, ks_status *result) {
+    if (!e || !result) return KS_E_ARG;
+    for (size_t i = 0; i < e->retired.size(); ++i) {
+        if (e->retired[i].first != ticket) continue;
+        *result = e->retired[i].second;
+        e->retired.erase(e->retired.begin() + i);
+        return KS_OK;
+    }
+    for (const EngReq &r : e->inflight)
+        if (r.ticket == ticket) return KS_E_BUSY;
+    return KS_E_ARG;
+}
+
 ks_status ks_engine_query(const ks_engine *e, ks_engine_stats *out) {
     if (!e || !out) return KS_E_ARG;
     std::memset(out, 0, sizeof(*out));

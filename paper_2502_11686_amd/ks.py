@@ -26,7 +26,7 @@ SYMBOLS = ("ks_workspace_bytes", "ks_supported", "ks_create", "ks_smooth", "ks_c
            "ks_smooth_cov", "ks_destroy", "ks_status_string", "ks_plan_layout",
            "ks_time_kernels", "ks_kernel_time", "ks_batch_workspace_bytes", "ks_batch_create",
            "ks_batch_smooth", "ks_batch_destroy", "ks_engine_create", "ks_engine_submit",
-           "ks_engine_step", "ks_engine_retired", "ks_engine_query", "ks_engine_destroy")
+           "ks_engine_step", "ks_engine_retired", "ks_engine_poll", "ks_engine_query", "ks_engine_destroy")
 KS_TIME_OFF, KS_TIME_FWD_LEVEL0, KS_TIME_BWD_LEVEL0, KS_TIME_FWD_ALL, KS_TIME_BWD_ALL = range(5)
 
 
@@ -113,6 +113,8 @@ def lib():
     L.ks_engine_retired.restype = ctypes.c_int
     L.ks_engine_retired.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64),
                                     ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int32)]
+    L.ks_engine_poll.restype = ctypes.c_int
+    L.ks_engine_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)]
     L.ks_engine_query.restype = ctypes.c_int
     L.ks_engine_query.argtypes = [vp, ctypes.POINTER(EngineStats)]
     L.ks_engine_destroy.restype = ctypes.c_int

@@ -135,6 +135,9 @@ def test_engine_admission_is_exact_footprint_first_fit():
     assert L.ks_engine_submit(h, ctypes.byref(d), ctypes.byref(nocov), 1, ctypes.byref(t)) == ks.KS_E_ARG
     cnt = ctypes.c_int32()
     assert L.ks_engine_retired(h, 0, None, None, ctypes.byref(cnt)) == ks.KS_OK and cnt.value == 0
+    res = ctypes.c_int()
+    assert L.ks_engine_poll(h, tickets[0], ctypes.byref(res)) == ks.KS_E_BUSY
+    assert L.ks_engine_poll(h, 10**9, ctypes.byref(res)) == ks.KS_E_ARG
     assert L.ks_engine_destroy(h) == ks.KS_OK
 
 
