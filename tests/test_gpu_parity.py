@@ -165,7 +165,8 @@ def test_errors():
 
 
 @pytest.mark.parametrize("k,n,m,cov", [(100, 6, 3, "dense"), (5000, 6, 3, "dense"), (777, 4, 2, "diag"),
-                                       (3000, 8, 4, "diag"), (1, 2, 1, "diag")])
+                                       (3000, 8, 4, "diag"), (1, 2, 1, "diag"), (201, 24, 12, "dense"),
+                                       (334, 32, 16, "diag"), (45, 48, 24, "dense")])
 def test_tail_kernels_equal_per_level_kernels(k, n, m, cov, monkeypatch):
     """The single-workgroup tail (top levels in one launch) computes exactly
     what one launch per level computes."""
