@@ -5,7 +5,7 @@
 // (load, whitening, steps 1 to 3, the fold of odd levels, the base) are in
 // ks_device_wg.h on a two-dimensional register tiling of each unit; this file
 // holds the backward levels -- back-substitution and Algorithm 2 -- with one
-// block row per workgroup, lane g owning column g of the R row, and the
+// block row per workgroup, the covariance products on FP64 MFMA, and the
 // kernel table of the family.
 #pragma once
 
@@ -16,7 +16,7 @@ namespace ks {
 template <int N>
 struct BGeo {
     static constexpr int W = 3 * N + 1;                    // columns of an R row
-    static constexpr int TBB = (W + 63) / 64 * 64;         // backward workgroup
+    static constexpr int TBB = 256;                        // backward workgroup (four MFMA wavefronts)
     static constexpr int RREC = N * (3 * N + 1);
     static constexpr int OREC = N * (N + 1);
     static constexpr int EREC = N * (2 * N + 1);
@@ -26,73 +26,62 @@ struct BGeo {
 
 // ------------------------------------------------------------ backward level
 
-// one block row (record t of level l); TBB threads, lane g < 3n+1 owns column g
-// of the R row: [R_ii | R_i,b | rho_i | R_i,a]
+typedef double mf_d4 __attribute__((ext_vector_type(4)));
+
+// LDS of one backward unit (doubles): region 0 holds R_ii, later P = T_I S_II,
+// later S_ii; then T = R_ii^{-1} [R_i,b | rho | R_i,a], RI = R_ii^{-1}, the
+// neighbour blocks S_aa, S_bb, S_ab, and 1 / R_ii(r, r)
+template <int N, bool COV>
+struct BSmem {
+    static constexpr int LR = N + 1;                 // row stride of R_ii, RI, S_ii, S blocks
+    static constexpr int LT = 2 * N + 1;             // row stride of T and P
+    static constexpr int R0 = COV ? N * LT : N * LR; // region 0
+    static constexpr int TO = R0;                    // T
+    static constexpr int RO = TO + N * LT;           // RI and the S blocks (covariances only)
+    static constexpr int DO = RO + (COV ? 4 * N * LR : 0);
+    static constexpr int PER = DO + 3 * N;           // 1 / R_ii(r, r), y_a, y_b
+};
+
+// One block row (record t of level l): back-substitution and Algorithm 2.
+//  1. T = R_ii^{-1} [R_i,b | rho_i | R_i,a] and RI = R_ii^{-1}: one right-hand
+//     side column per thread, column-oriented substitution (independent
+//     updates after each x_r, so the dependent chain is n steps long).
+//  2. y_i = z - T_a y_a - T_b y_b.
+//  3. P = T_I S_II (T_I = [T_a | T_b], n x 2n; S_II the 2n x 2n covariance of
+//     the neighbours, S_ab from whichever of them sits one level up) and
+//     S_ii = RI RI^T + P T_I^T, both as 16x16x4 FP64 MFMA tiles (rows padded
+//     to a multiple of 16); -P gives the blocks S_i,a S_i,b kept for lower
+//     levels, S_ii is symmetrized on the way out.
+// 256 threads; every thread must call it the same number of times.
 template <int N, bool DO_Y, bool DO_COV, class TR>
 __device__ __forceinline__ void blk_bwd_unit(const BwdArgs &a, int l, int64_t t, int64_t units,
                                              bool store_s, double *sm) {
     using BG = BGeo<N>;
+    using SM = BSmem<N, DO_COV>;
     constexpr int W = BG::W;
-    constexpr int TW = 2 * N + 1;   // T columns [T+ | z | T-]
-    double *Rd = sm;                // R_ii, later S_ii
-    double *TT = Rd + N * N;
-    double *RI = TT + N * TW;
-    double *PP = RI + N * N;
-    const int gl = threadIdx.x;
+    constexpr int LR = SM::LR, LT = SM::LT;
+    constexpr int NT = BG::TBB;
+    double *Rd = sm;                 // R_ii; then P; then S_ii
+    double *TT = sm + SM::TO;        // [T_b | z | T_a]
+    double *RI = sm + SM::RO;
+    double *SA = RI + N * LR;        // S_aa, S_bb, S_ab (each n x LR)
+    double *SB = SA + N * LR;
+    double *SX = SB + N * LR;
+    double *DI = sm + SM::DO;        // 1 / R_ii(r, r), then y_a, y_b
+    const int g = threadIdx.x;
     const bool valid = t < units;
     const int64_t i = ((2 * t + 1) << l) - 1;
     const int64_t aa = i - ((int64_t)1 << l), bb = i + ((int64_t)1 << l);
     const bool va = valid && aa >= 0, vb = valid && bb <= a.k;
     const TR *rec = slot<TR>(a.rrows_all, a.rec_off[l] + t, BG::RREC);
 
-    double x[N];
-    if (gl < W) {
-#pragma unroll
-        for (int r = 0; r < N; ++r) x[r] = valid ? double(rec[r * W + gl]) : (r == gl ? 1.0 : 0.0);
-        if (gl < N) {
-#pragma unroll
-            for (int r = 0; r < N; ++r) Rd[r * N + gl] = x[r];
-        }
-    }
-    __syncthreads();
-    if (gl < W && (DO_COV || gl >= N)) {
-        if (gl < N) {
-#pragma unroll
-            for (int r = 0; r < N; ++r) x[r] = r == gl ? 1.0 : 0.0;
-        }
-#pragma unroll
-        for (int r = N - 1; r >= 0; --r) {
-            double acc = x[r];
-#pragma unroll
-            for (int s = r + 1; s < N; ++s) acc = fma(-Rd[r * N + s], x[s], acc);
-            x[r] = acc * rcp_nr(Rd[r * N + r]);
-        }
-        if (gl < N) {
-#pragma unroll
-            for (int r = 0; r < N; ++r) RI[r * N + gl] = x[r];
-        } else {
-#pragma unroll
-            for (int r = 0; r < N; ++r) TT[r * TW + (gl - N)] = x[r];
-        }
-    }
-    __syncthreads();
-    auto TI = [&](int r, int d) -> double {
-        return d < N ? TT[r * TW + N + 1 + d] : TT[r * TW + (d - N)];
-    };
-    if constexpr (DO_Y) {
-        if (valid && gl < N) {
-            double y0 = TT[gl * TW + N], y1 = 0.0;
-#pragma unroll 4
-            for (int d = 0; d < N; ++d) {
-                if (va) y0 = fma(-TI(gl, d), a.u_in[aa * N + d], y0);
-                if (vb) y1 = fma(-TI(gl, N + d), a.u_in[bb * N + d], y1);
-            }
-            a.u_out[i * N + gl] = y0 + y1;
-        }
-    }
+    // the neighbours' covariance blocks are fetched first and land in LDS after
+    // the substitution, so their latency overlaps it
+    constexpr int SPT = DO_COV ? (N * N + NT - 1) / NT : 1;
+    double sa_[SPT], sb_[SPT], sx_[SPT];
+    const double *sab = nullptr;
+    bool trans = false;
     if constexpr (DO_COV) {
-        const double *sab = nullptr;
-        bool trans = false;
         if (va && vb) {
             const int la = __builtin_ctzll((unsigned long long)(aa + 1));
             if (la == l + 1) {
@@ -102,74 +91,205 @@ __device__ __forceinline__ void blk_bwd_unit(const BwdArgs &a, int l, int64_t t,
                 trans = true;
             }
         }
-        // S_II(d, c) for d, c < 2n
+#pragma unroll
+        for (int u = 0; u < SPT; ++u) {
+            const int idx = g + NT * u;
+            const bool in = idx < N * N;
+            sa_[u] = (in && va) ? a.cov[aa * N * N + idx] : 0.0;
+            sb_[u] = (in && vb) ? a.cov[bb * N * N + idx] : 0.0;
+            sx_[u] = (in && sab) ? sab[idx] : 0.0;
+        }
+    }
+
+    // the R row: every load issued before the first LDS store
+    constexpr int RPL = (N * W + NT - 1) / NT;
+    double rv[RPL];
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) {
+        const int idx = g + NT * u;
+        rv[u] = (idx < N * W && valid) ? double(rec[idx]) : 0.0;
+    }
+    double ya = 0.0, yb = 0.0;  // neighbour states, element g
+    if (DO_Y && g < N) {
+        ya = va ? a.u_in[aa * N + g] : 0.0;
+        yb = vb ? a.u_in[bb * N + g] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) {
+        const int idx = g + NT * u;
+        if (idx < N * W) {
+            const int r = idx / W, c = idx - r * W;
+            const double v = valid ? rv[u] : (c == r ? 1.0 : 0.0);
+            if (c < N) Rd[r * LR + c] = v;
+            else TT[r * LT + (c - N)] = v;
+        }
+    }
+    if (DO_Y && g < N) {
+        DI[N + g] = ya;
+        DI[2 * N + g] = yb;
+    }
+    __syncthreads();
+    if (g < N) DI[g] = rcp_nr(Rd[g * LR + g]);
+    __syncthreads();
+    if (g < W && (DO_COV || g >= N)) {
+        double x[N];
+#pragma unroll
+        for (int r = 0; r < N; ++r) x[r] = g < N ? (r == g ? 1.0 : 0.0) : TT[r * LT + (g - N)];
+#pragma unroll
+        for (int r = N - 1; r >= 0; --r) {
+            const double xr = x[r] * DI[r];
+            x[r] = xr;
+#pragma unroll
+            for (int s = 0; s < r; ++s) x[s] = fma(-Rd[s * LR + r], xr, x[s]);
+        }
+        if (g < N) {
+#pragma unroll
+            for (int r = 0; r < N; ++r) RI[r * LR + g] = x[r];
+        } else {
+#pragma unroll
+            for (int r = 0; r < N; ++r) TT[r * LT + (g - N)] = x[r];
+        }
+    }
+    if constexpr (DO_COV) {
+        // S_ab(rr, cc) into SX[rr][cc] (S_ab is stored as S+ of a, or as S- of b, transposed)
+#pragma unroll
+        for (int u = 0; u < SPT; ++u) {
+            const int idx = g + NT * u;
+            if (idx < N * N) {
+                const int r = idx / N, c = idx - r * N;
+                SA[r * LR + c] = sa_[u];
+                SB[r * LR + c] = sb_[u];
+                if (trans) SX[c * LR + r] = sx_[u];
+                else SX[r * LR + c] = sx_[u];
+            }
+        }
+    }
+    __syncthreads();
+    // T_I(r, d): d < n the a-part (T_a), d >= n the b-part (T_b)
+    auto TI = [&](int r, int d) -> double {
+        return d < N ? TT[r * LT + N + 1 + d] : TT[r * LT + (d - N)];
+    };
+    if constexpr (DO_Y) {
+        if (valid && g < N) {
+            const double *ua = DI + N, *ub = DI + 2 * N;  // zero where a neighbour is missing
+            double y0 = TT[g * LT + N], y1 = 0.0;
+#pragma unroll 8
+            for (int d = 0; d < N; ++d) {
+                y0 = fma(-TI(g, d), ua[d], y0);
+                y1 = fma(-TI(g, N + d), ub[d], y1);
+            }
+            a.u_out[i * N + g] = y0 + y1;
+        }
+    }
+    if constexpr (DO_COV) {
+        constexpr int TM = (N + 15) / 16;      // row tiles (rows >= n are zero)
+        constexpr int TC = 2 * N / 16;         // column tiles of P
+        constexpr int QP = (TM * TC + 3) / 4;  // P tiles per wavefront
+        constexpr int QS = (TM * TM + 3) / 4;  // S tiles per wavefront
+        static_assert(2 * N % 16 == 0, "n must be a multiple of 8");
+        const int wave = g >> 6, lane = g & 63;
+        const int lr = lane & 15, lk = lane >> 4;
+        // S_II(d, c) for d, c < 2n (missing neighbours give zero blocks)
         auto SII = [&](int d, int c) -> double {
-            if (d < N && c < N) return va ? a.cov[aa * N * N + d * N + c] : 0.0;
-            if (d >= N && c >= N) return vb ? a.cov[bb * N * N + (d - N) * N + (c - N)] : 0.0;
-            if (!sab) return 0.0;
-            const int rr = d < N ? d : c, cc = d < N ? c - N : d - N;  // S_ab(rr, cc)
-            return trans ? sab[cc * N + rr] : sab[rr * N + cc];
+            if (d < N && c < N) return SA[d * LR + c];
+            if (d >= N && c >= N) return SB[(d - N) * LR + (c - N)];
+            return d < N ? SX[d * LR + (c - N)] : SX[c * LR + (d - N)];
         };
-        if (gl < 2 * N) {
-            double p[N];
+        // P = T_I S_II.  MFMA 16x16x4 FP64 operands: lane l holds A(l % 16, l / 16)
+        // and B(l / 16, l % 16); the result D(l / 16 + 4 j, l % 16) in element j.
+        // Tile q = ti + TM tj runs on wavefront q % 4.
+        mf_d4 acc[QP];
 #pragma unroll
-            for (int r = 0; r < N; ++r) p[r] = 0.0;
+        for (int u = 0; u < QP; ++u) acc[u] = mf_d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll 2
-            for (int d = 0; d < 2 * N; ++d) {
-                const double s = SII(d, gl);
+        for (int kk = 0; kk < 2 * N / 4; ++kk) {
+            const int d = 4 * kk + lk;
 #pragma unroll
-                for (int r = 0; r < N; ++r) p[r] = fma(TI(r, d), s, p[r]);
+            for (int u = 0; u < QP; ++u) {
+                const int q = wave + 4 * u;
+                if (q < TM * TC) {
+                    const int ti = q % TM, tj = q / TM;
+                    const int r = 16 * ti + lr;
+                    const double av = r < N ? TI(r, d) : 0.0;
+                    const double bv = SII(d, 16 * tj + lr);
+                    acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[u], 0, 0, 0);
+                }
             }
+        }
+        __syncthreads();  // R_ii no longer read: region 0 takes P
+        double *PP = Rd;
 #pragma unroll
-            for (int r = 0; r < N; ++r) PP[r * 2 * N + gl] = p[r];
-            if (valid && store_s) {
-                const int64_t ri = a.rec_off[l] + t - a.spm_first;
-                double *dst = a.spm + ri * 2 * N * N + (gl < N ? 0 : N * N);
-                const int c = gl < N ? gl : gl - N;
+        for (int u = 0; u < QP; ++u) {
+            const int q = wave + 4 * u;
+            if (q < TM * TC) {
+                const int ti = q % TM, tj = q / TM;
+                const int c = 16 * tj + lr;
 #pragma unroll
-                for (int r = 0; r < N; ++r) dst[r * N + c] = -p[r];
+                for (int j = 0; j < 4; ++j) {
+                    const int r = 16 * ti + lk + 4 * j;
+                    if (r < N) {
+                        PP[r * LT + c] = acc[u][j];
+                        if (valid && store_s) {
+                            const int64_t ri = a.rec_off[l] + t - a.spm_first;
+                            double *dst = a.spm + ri * 2 * N * N + (c < N ? 0 : N * N);
+                            dst[r * N + (c < N ? c : c - N)] = -acc[u][j];
+                        }
+                    }
+                }
             }
         }
         __syncthreads();
-        if (gl < N) {
-            double s[N];
+        // S_ii = RI RI^T + P T_I^T: A = [RI | P] (n x 3n), B(k, c) = [RI | T_I](c, k)
+        mf_d4 sc[QS];
 #pragma unroll
-            for (int r = 0; r < N; ++r) s[r] = 0.0;
+        for (int u = 0; u < QS; ++u) sc[u] = mf_d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll 2
-            for (int q = 0; q < N; ++q) {
-                const double rc = RI[gl * N + q];
+        for (int kk = 0; kk < 3 * N / 4; ++kk) {
+            const int k = 4 * kk + lk;
 #pragma unroll
-                for (int r = 0; r < N; ++r) s[r] = fma(RI[r * N + q], rc, s[r]);
+            for (int u = 0; u < QS; ++u) {
+                const int q = wave + 4 * u;
+                if (q < TM * TM) {
+                    const int ti = q % TM, tj = q / TM;
+                    const int r = 16 * ti + lr, c = 16 * tj + lr;
+                    double av = 0.0, bv = 0.0;
+                    if (r < N) av = k < N ? RI[r * LR + k] : PP[r * LT + (k - N)];
+                    if (c < N) bv = k < N ? RI[c * LR + k] : TI(c, k - N);
+                    sc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, sc[u], 0, 0, 0);
+                }
             }
-#pragma unroll 2
-            for (int d = 0; d < 2 * N; ++d) {
-                const double tc = TI(gl, d);
+        }
+        __syncthreads();  // P no longer read: region 0 takes S_ii
+        double *SS = Rd;
 #pragma unroll
-                for (int r = 0; r < N; ++r) s[r] = fma(PP[r * 2 * N + d], tc, s[r]);
+        for (int u = 0; u < QS; ++u) {
+            const int q = wave + 4 * u;
+            if (q < TM * TM) {
+                const int ti = q % TM, tj = q / TM;
+                const int c = 16 * tj + lr;
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int r = 16 * ti + lk + 4 * j;
+                    if (r < N && c < N) SS[r * LR + c] = sc[u][j];
+                }
             }
-#pragma unroll
-            for (int r = 0; r < N; ++r) Rd[r * N + gl] = s[r];
         }
         __syncthreads();
-        if (valid && gl < N) {
-#pragma unroll
-            for (int r = 0; r < N; ++r)
-                a.cov[i * N * N + r * N + gl] = 0.5 * (Rd[r * N + gl] + Rd[gl * N + r]);
+        if (valid) {
+            for (int idx = g; idx < N * N; idx += NT) {
+                const int r = idx / N, c = idx - r * N;
+                a.cov[i * N * N + idx] = 0.5 * (SS[r * LR + c] + SS[c * LR + r]);
+            }
         }
     }
     __syncthreads();
 }
 
-template <int N>
-struct BSmem {
-    static constexpr int PER = N * N + N * (2 * N + 1) + N * N + 2 * N * N;
-};
-
 template <int N, bool DO_Y, bool DO_COV, class TR, bool BATCH>
 __global__ __launch_bounds__(BGeo<N>::TBB) void k_blk_backward(BwdArgs a0, const BwdArgs *tab,
                                                                BlockMap bm) {
     const BwdArgs &a = BATCH ? tab[bm.item[blockIdx.x]] : a0;
-    __shared__ double sm[BSmem<N>::PER];
+    __shared__ double sm[BSmem<N, DO_COV>::PER];
     const int l = BATCH ? bm.level[blockIdx.x] : a.level;
     const int64_t blk = BATCH ? bm.blk[blockIdx.x] : (int64_t)blockIdx.x;
     blk_bwd_unit<N, DO_Y, DO_COV, TR>(a, l, blk, (a.Nl[l] + 1) / 2, a.store_s && l >= 1, sm);
@@ -179,7 +299,7 @@ template <int N, bool DO_Y, bool DO_COV, bool BATCH>
 __global__ __launch_bounds__(BGeo<N>::TBB) void k_blk_bwd_tail(BwdArgs a0, const BwdArgs *tab,
                                                                BlockMap bm) {
     const BwdArgs &a = BATCH ? tab[bm.item[blockIdx.x]] : a0;
-    __shared__ double sm[BSmem<N>::PER];
+    __shared__ double sm[BSmem<N, DO_COV>::PER];
     for (int l = a.level; l >= a.l_lo; --l) {
         const int64_t units = (a.Nl[l] + 1) / 2;
         for (int64_t t = 0; t < units; ++t)
