@@ -26,8 +26,10 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fwd_level0_n6_k100000.json")
+# sources of the level-0 forward kernel of the benchmark workload (n = 6): a
+# traffic summary taken on other sources is not used
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2502_11686_amd", "csrc", f)
-               for f in ("ks_device.h", "ks_device_blk.h", "ks_internal.h")]
+               for f in ("ks_device.h", "ks_internal.h", "ks_inst_n6.hip")]
 
 
 WORKLOAD_NAMES = {
@@ -101,6 +103,8 @@ def main():
                     help="serving workload: engine workspace (request regions) in GB; inputs and outputs "
                          "are admitted against the same amount again")
     ap.add_argument("--k", type=int, default=None)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain device copy of 1 GiB (5 launches) for HBM-counter calibration")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     args = ap.parse_args()
@@ -114,6 +118,15 @@ def main():
 
     from paper_2502_11686_amd import gen, ks
 
+    if args.calibrate_copy:
+        # a plain copy kernel of known size: 1 GiB read and 1 GiB written per launch
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration_copy_bytes": src.numel() * 8, "launches": 5}), flush=True)
+        return
     if args.workload == 3:
         return batch_bench(args)
     if args.workload == 4:
