@@ -166,6 +166,30 @@ typedef enum {
 ks_status ks_time_kernels(ks_plan *plan, int32_t kind);
 ks_status ks_kernel_time(const ks_plan *plan, double *total_ms, int64_t *count);
 
+/* ---------------------------------------------------------------- tuning
+ *
+ * The schedule's free choices, per state dimension n (1..64) and precision
+ * form: the top levels that need at most fwd_tail_passes (bwd_tail_passes)
+ * passes of the single-workgroup forward (backward) tail kernel run inside
+ * it instead of one launch each (0: the base level only), and in the FP32
+ * form the levels with more than fp32_switch_columns block columns run in
+ * FP32.  None of them changes what is computed beyond rounding order: the
+ * tail and per-level kernels do the same arithmetic, so FP64 results are
+ * bitwise independent of the pass counts.  Defaults 2, 2, 1024; an autotuned
+ * table is applied by the Python binding; the environment variables
+ * KS_TAIL_PASSES (both pass counts) and KS_FP32_SWITCH override every entry.
+ * Plans, batches and engine requests read the table when they are created;
+ * not safe to call concurrently with those. */
+ks_status ks_set_tuning(int32_t n, int32_t precision, int32_t fwd_tail_passes, int32_t bwd_tail_passes,
+                        int64_t fp32_switch_columns);
+/* effective values (environment overrides applied) */
+ks_status ks_get_tuning(int32_t n, int32_t precision, int32_t *fwd_tail_passes, int32_t *bwd_tail_passes,
+                        int64_t *fp32_switch_columns);
+/* the plan's schedule: number of FP32 levels, first level of the forward tail
+ * launch, lowest level of the backward tail launch (states + covariances) */
+ks_status ks_plan_schedule(const ks_plan *plan, int32_t *fp32_levels, int32_t *fwd_tail_level,
+                           int32_t *bwd_tail_level);
+
 /* ---------------------------------------------------------------- batches
  *
  * Many independent problems (any mix of k, n, m, layouts and precision forms)

@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -102,8 +103,10 @@ struct ks_plan {
     Layout lo;
     bool smoothed;
     unsigned host_flags;   // status word copied back after each call
-    int tail_passes;       // single-workgroup tail: levels needing <= this many passes
     int l_switch;          // FP32 form: levels below this one run in FP32 (0 = none)
+    int l0;                // first level of the forward tail launch
+    int l1[3];             // lowest level of the backward tail launch, per backward mode
+    double rank_tol;
     // instrumentation (ks_time_kernels)
     int time_kind;
     bool time_armed;       // events of the current call were recorded
@@ -147,6 +150,54 @@ int tail_start(const Layout &lo, int per_pass, int passes, bool backward) {
     return lo.L;
 }
 
+// Schedule choices per (state dimension, precision form): how many unit passes
+// of the single-workgroup forward / backward tail kernels the top levels may
+// take, and (FP32 form) above how many columns a level runs in FP32.  Set by
+// ks_set_tuning (an autotuned table); KS_TAIL_PASSES and KS_FP32_SWITCH in the
+// environment override every entry.
+struct Tuning {
+    int32_t fwd_passes, bwd_passes;
+    int64_t switch_cols;
+};
+constexpr int kTuneMaxN = 64;
+std::mutex g_tune_mu;
+Tuning g_tune[kTuneMaxN + 1][2];
+bool g_tune_set[kTuneMaxN + 1][2];
+
+Tuning tuning_for(int n, int precision) {
+    Tuning t{2, 2, 1024};
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        if (n >= 0 && n <= kTuneMaxN && precision >= 0 && precision < 2 && g_tune_set[n][precision])
+            t = g_tune[n][precision];
+    }
+    if (const char *e = std::getenv("KS_TAIL_PASSES")) t.fwd_passes = t.bwd_passes = std::atoi(e);
+    if (const char *e = std::getenv("KS_FP32_SWITCH")) t.switch_cols = std::atoll(e);
+    return t;
+}
+
+// the level schedule of one problem: FP32 levels, first forward tail level,
+// lowest backward tail level (identical for a plan, a batch and the engine)
+struct Schedule {
+    int l_switch, l0, l1;
+    double rank_tol;
+};
+
+Schedule make_schedule(const ks_desc &d, const ks::KernelSet *kset, const Layout &lo, int bwd_mode) {
+    const Tuning tu = tuning_for(d.n, d.precision);
+    Schedule sc{};
+    sc.l_switch = 0;
+    if (d.precision == KS_FP32_FORM)
+        while (sc.l_switch < lo.L && lo.Nl[sc.l_switch] > tu.switch_cols) ++sc.l_switch;
+    int l0 = tail_start(lo, kset->upb_fwd_tail, tu.fwd_passes, false);
+    if (sc.l_switch > 0 && l0 <= sc.l_switch) l0 = sc.l_switch + 1;  // the tail reads FP64 records only
+    sc.l0 = l0 > lo.L ? lo.L : l0;                                    // the base always runs in the tail
+    int l1 = tail_start(lo, kset->upb_bwd_tail[bwd_mode], tu.bwd_passes, true);
+    sc.l1 = l1 < sc.l_switch ? sc.l_switch : l1;
+    sc.rank_tol = 64.0 * (sc.l_switch > 0 ? 1.1920928955078125e-07 : 2.220446049250313e-16);
+    return sc;
+}
+
 void enqueue_forward(ks_plan *p, const double *H, const double *F, const double *c,
                      const double *K, const double *G, const double *o, const double *C) {
     const Layout &lo = p->lo;
@@ -158,10 +209,8 @@ void enqueue_forward(ks_plan *p, const double *H, const double *F, const double 
     unsigned *flags = reinterpret_cast<unsigned *>(p->ws + lo.off_flags);
     ks::launch_clear_flags(flags, p->stream);
     mark(p, KS_TIME_FWD_ALL, 0);
-    int l0 = tail_start(lo, p->kset->upb_fwd_tail, p->tail_passes, false);
+    const int l0 = p->l0;
     const int ls = p->l_switch;
-    if (ls > 0 && l0 <= ls) l0 = ls + 1;  // the tail reads FP64 records only
-    if (l0 > lo.L) l0 = lo.L;             // the base level always runs in the tail kernel
     ks::FwdArgs a{};
     a.k = p->d.k;
     a.m = p->d.m;
@@ -199,7 +248,7 @@ void enqueue_forward(ks_plan *p, const double *H, const double *F, const double 
     ta.rrows = rrows;
     ta.slots = slots;
     ta.nprev = lo.slot_off[l0];
-    ta.rank_tol = 64.0 * (p->l_switch > 0 ? 1.1920928955078125e-07 : 2.220446049250313e-16);
+    ta.rank_tol = p->rank_tol;
     for (int l = 0; l <= lo.L; ++l) {
         ta.sys_off[l] = lo.sys_off[l];
         ta.rec_off[l] = lo.rec_off[l];
@@ -227,8 +276,7 @@ void enqueue_backward(ks_plan *p, double *u_out, double *cov_out) {
         b.rec_off[l] = lo.rec_off[l];
         b.Nl[l] = lo.Nl[l];
     }
-    int l1 = tail_start(lo, p->kset->upb_bwd_tail[mode], p->tail_passes, true);
-    if (l1 < p->l_switch) l1 = p->l_switch;  // the tail reads FP64 records only
+    const int l1 = p->l1[mode];
     mark(p, KS_TIME_BWD_ALL, 0);
     if (l1 <= lo.L) {
         b.level = lo.L;
@@ -310,14 +358,13 @@ ks_status ks_create(const ks_desc *desc, void *workspace, size_t ws_bytes, void 
     p->ev_made = false;
     p->time_ms = 0.0;
     p->time_count = 0;
-    p->tail_passes = 2;
-    if (const char *e = std::getenv("KS_TAIL_PASSES")) p->tail_passes = std::atoi(e);
-    // FP32 form: levels with more than switch_cols columns run in FP32
-    int64_t switch_cols = 1024;
-    if (const char *e = std::getenv("KS_FP32_SWITCH")) switch_cols = std::atoll(e);
-    p->l_switch = 0;
-    if (desc->precision == KS_FP32_FORM)
-        while (p->l_switch < lo.L && lo.Nl[p->l_switch] > switch_cols) ++p->l_switch;
+    for (int mode = 0; mode < 3; ++mode) {
+        const Schedule sc = make_schedule(*desc, kset, lo, mode);
+        p->l_switch = sc.l_switch;
+        p->l0 = sc.l0;
+        p->l1[mode] = sc.l1;
+        p->rank_tol = sc.rank_tol;
+    }
     *out = p;
     return KS_OK;
 }
@@ -381,6 +428,38 @@ const char *ks_status_string(ks_status s) {
     case KS_E_BUSY: return "the engine cannot admit the request now (workspace, tables or status words in use)";
     }
     return "unknown status";
+}
+
+ks_status ks_set_tuning(int32_t n, int32_t precision, int32_t fwd_tail_passes, int32_t bwd_tail_passes,
+                        int64_t fp32_switch_columns) {
+    if (n < 1 || n > kTuneMaxN || (precision != KS_FP64 && precision != KS_FP32_FORM) || fwd_tail_passes < 0 ||
+        bwd_tail_passes < 0 || fp32_switch_columns < 1)
+        return KS_E_ARG;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune[n][precision] = Tuning{fwd_tail_passes, bwd_tail_passes, fp32_switch_columns};
+    g_tune_set[n][precision] = true;
+    return KS_OK;
+}
+
+ks_status ks_get_tuning(int32_t n, int32_t precision, int32_t *fwd_tail_passes, int32_t *bwd_tail_passes,
+                        int64_t *fp32_switch_columns) {
+    if (n < 1 || n > kTuneMaxN || (precision != KS_FP64 && precision != KS_FP32_FORM) || !fwd_tail_passes ||
+        !bwd_tail_passes || !fp32_switch_columns)
+        return KS_E_ARG;
+    const Tuning t = tuning_for(n, precision);
+    *fwd_tail_passes = t.fwd_passes;
+    *bwd_tail_passes = t.bwd_passes;
+    *fp32_switch_columns = t.switch_cols;
+    return KS_OK;
+}
+
+ks_status ks_plan_schedule(const ks_plan *p, int32_t *fp32_levels, int32_t *fwd_tail_level,
+                           int32_t *bwd_tail_level) {
+    if (!p || !fp32_levels || !fwd_tail_level || !bwd_tail_level) return KS_E_ARG;
+    *fp32_levels = p->l_switch;
+    *fwd_tail_level = p->l0;
+    *bwd_tail_level = p->l1[ks::BWD_BOTH];
+    return KS_OK;
 }
 
 ks_status ks_plan_layout(const ks_plan *p, ks_layout *out) {
@@ -729,10 +808,6 @@ static ks_status batch_setup(int32_t count, const ks_desc *descs, ks_batch *b, s
     size_t off = 0;
     b->count = count;
     b->probs.resize(count);
-    int tail_passes = 2;
-    if (const char *e = std::getenv("KS_TAIL_PASSES")) tail_passes = std::atoi(e);
-    int64_t switch_cols = 1024;
-    if (const char *e = std::getenv("KS_FP32_SWITCH")) switch_cols = std::atoll(e);
     for (int i = 0; i < count; ++i) {
         BatchProblem &pr = b->probs[i];
         pr.d = descs[i];
@@ -742,18 +817,11 @@ static ks_status batch_setup(int32_t count, const ks_desc *descs, ks_batch *b, s
         if (!make_layout(&pr.d, pr.kset, &pr.lo)) return KS_E_ARG;
         pr.ws_off = off;
         off = align_up(off + pr.lo.total);
-        pr.l_switch = 0;
-        if (pr.d.precision == KS_FP32_FORM)
-            while (pr.l_switch < pr.lo.L && pr.lo.Nl[pr.l_switch] > switch_cols) ++pr.l_switch;
-        int l0 = tail_start(pr.lo, pr.kset->upb_fwd_tail, tail_passes, false);
-        if (pr.l_switch > 0 && l0 <= pr.l_switch) l0 = pr.l_switch + 1;
-        if (l0 > pr.lo.L) l0 = pr.lo.L;
-        pr.l0 = l0;
-        const int mode = ks::BWD_BOTH;  // the tail start does not depend on the mode's unit count here
-        int l1 = tail_start(pr.lo, pr.kset->upb_bwd_tail[mode], tail_passes, true);
-        if (l1 < pr.l_switch) l1 = pr.l_switch;
-        pr.l1 = l1;
-        pr.rank_tol = 64.0 * (pr.l_switch > 0 ? 1.1920928955078125e-07 : 2.220446049250313e-16);
+        const Schedule sc = make_schedule(pr.d, pr.kset, pr.lo, ks::BWD_BOTH);
+        pr.l_switch = sc.l_switch;
+        pr.l0 = sc.l0;
+        pr.l1 = sc.l1;
+        pr.rank_tol = sc.rank_tol;
     }
     plan_batch(b);
     b->off_fwd = off;
@@ -919,8 +987,6 @@ struct ks_engine {
     std::vector<std::pair<uint64_t, ks_status>> retired;
     size_t tab_used;       // sum of tab_need over in-flight requests
     uint64_t next_ticket, ticks;
-    int tail_passes;
-    int64_t switch_cols;
     std::vector<char> staging;
     std::vector<unsigned> hflags;
 };
@@ -1098,10 +1164,6 @@ ks_status ks_engine_create(void *workspace, size_t ws_bytes, void *hip_stream, k
     e->tab_used = kEngTabFixed;
     e->next_ticket = 1;
     e->ticks = 0;
-    e->tail_passes = 2;
-    if (const char *v = std::getenv("KS_TAIL_PASSES")) e->tail_passes = std::atoi(v);
-    e->switch_cols = 1024;
-    if (const char *v = std::getenv("KS_FP32_SWITCH")) e->switch_cols = std::atoll(v);
     e->hflags.assign(kEngSlots, 0u);
     *out = e;
     return KS_OK;
@@ -1118,18 +1180,14 @@ ks_status ks_engine_submit(ks_engine *e, const ks_desc *desc, const ks_io *io, i
     if (!io->u_out || (want_cov && !io->cov_out)) return KS_E_ARG;
     if (desc->k > 0 && (!io->F || !io->c || !io->K)) return KS_E_ARG;
     if (desc->m > 0 && (!io->G || !io->o || !io->C)) return KS_E_ARG;
-    // schedule, exactly as a single plan (and a batch) derives it
-    pr.l_switch = 0;
-    if (desc->precision == KS_FP32_FORM)
-        while (pr.l_switch < pr.lo.L && pr.lo.Nl[pr.l_switch] > e->switch_cols) ++pr.l_switch;
-    int l0 = tail_start(pr.lo, pr.kset->upb_fwd_tail, e->tail_passes, false);
-    if (pr.l_switch > 0 && l0 <= pr.l_switch) l0 = pr.l_switch + 1;
-    pr.l0 = std::min(l0, pr.lo.L);
-    int l1 = tail_start(pr.lo, pr.kset->upb_bwd_tail[ks::BWD_BOTH], e->tail_passes, true);
-    pr.l1 = std::max(l1, pr.l_switch);
-    pr.rank_tol = 64.0 * (pr.l_switch > 0 ? 1.1920928955078125e-07 : 2.220446049250313e-16);
-    // bound on the request's share of one tick's tables
+    // schedule, exactly as a single plan derives it
     const int mode = want_cov ? ks::BWD_BOTH : ks::BWD_Y;
+    const Schedule sc = make_schedule(*desc, pr.kset, pr.lo, mode);
+    pr.l_switch = sc.l_switch;
+    pr.l0 = sc.l0;
+    pr.l1 = sc.l1;
+    pr.rank_tol = sc.rank_tol;
+    // bound on the request's share of one tick's tables
     int64_t maxb = 1;
     for (int l = 0; l < pr.l0; ++l) maxb = std::max(maxb, fwd_blocks(pr, l));
     for (int l = 0; l < std::min(pr.l1, pr.lo.L + 1); ++l) maxb = std::max(maxb, bwd_blocks(pr, l, mode));

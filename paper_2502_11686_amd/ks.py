@@ -16,6 +16,7 @@ import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libks.so")
+TUNE_PATH = os.path.join(_HERE, "tune_mi355x.json")  # autotuned schedule table (autotune.py)
 
 KS_OK, KS_E_ARG, KS_E_WORKSPACE, KS_E_NOT_SPD, KS_E_RANK = 0, -1, -2, -3, -4
 KS_E_NONFINITE, KS_E_HIP, KS_E_ORDER, KS_E_BUSY = -5, -6, -7, -8
@@ -26,7 +27,8 @@ SYMBOLS = ("ks_workspace_bytes", "ks_supported", "ks_create", "ks_smooth", "ks_c
            "ks_smooth_cov", "ks_destroy", "ks_status_string", "ks_plan_layout",
            "ks_time_kernels", "ks_kernel_time", "ks_batch_workspace_bytes", "ks_batch_create",
            "ks_batch_smooth", "ks_batch_destroy", "ks_engine_create", "ks_engine_submit",
-           "ks_engine_step", "ks_engine_retired", "ks_engine_poll", "ks_engine_query", "ks_engine_destroy")
+           "ks_engine_step", "ks_engine_retired", "ks_engine_poll", "ks_engine_query", "ks_engine_destroy",
+           "ks_set_tuning", "ks_get_tuning", "ks_plan_schedule")
 KS_TIME_OFF, KS_TIME_FWD_LEVEL0, KS_TIME_BWD_LEVEL0, KS_TIME_FWD_ALL, KS_TIME_BWD_ALL = range(5)
 
 
@@ -119,8 +121,47 @@ def lib():
     L.ks_engine_query.argtypes = [vp, ctypes.POINTER(EngineStats)]
     L.ks_engine_destroy.restype = ctypes.c_int
     L.ks_engine_destroy.argtypes = [vp]
+    L.ks_set_tuning.restype = ctypes.c_int
+    L.ks_set_tuning.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64]
+    L.ks_get_tuning.restype = ctypes.c_int
+    L.ks_get_tuning.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]
+    L.ks_plan_schedule.restype = ctypes.c_int
+    L.ks_plan_schedule.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                   ctypes.POINTER(ctypes.c_int32)]
     _lib = L
+    if not os.environ.get("KS_NO_TUNE"):
+        path = os.environ.get("KS_TUNE_FILE", TUNE_PATH)
+        if os.path.exists(path):
+            load_tuning(path)
     return L
+
+
+def set_tuning(n: int, fp32: bool, fwd_tail_passes: int, bwd_tail_passes: int, fp32_switch_columns: int = 1024):
+    st = lib().ks_set_tuning(int(n), KS_FP32_FORM if fp32 else KS_FP64, int(fwd_tail_passes),
+                             int(bwd_tail_passes), int(fp32_switch_columns))
+    if st != KS_OK:
+        raise KsError(st, "ks_set_tuning")
+
+
+def get_tuning(n: int, fp32: bool = False) -> dict:
+    f, b, w = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+    st = lib().ks_get_tuning(int(n), KS_FP32_FORM if fp32 else KS_FP64, ctypes.byref(f), ctypes.byref(b),
+                             ctypes.byref(w))
+    if st != KS_OK:
+        raise KsError(st, "ks_get_tuning")
+    return dict(fwd_tail_passes=f.value, bwd_tail_passes=b.value, fp32_switch_columns=w.value)
+
+
+def load_tuning(path: str) -> int:
+    """Apply a tuning table written by autotune.py; returns the entries applied."""
+    import json
+    with open(path) as fh:
+        table = json.load(fh)
+    for e in table.get("entries", []):
+        set_tuning(e["n"], e["form"] == "fp32", e["fwd_tail_passes"], e["bwd_tail_passes"],
+                   e.get("fp32_switch_columns", 1024))
+    return len(table.get("entries", []))
 
 
 def make_desc(k: int, n: int, m: int, K_diag: bool, C_diag: bool, fp32: bool = False) -> Desc:
@@ -257,6 +298,14 @@ class Plan:
         if st != KS_OK:
             raise KsError(st, "ks_covariances")
         return cov
+
+    def schedule(self) -> dict:
+        """FP32 levels, first forward-tail level, lowest backward-tail level."""
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        st = lib().ks_plan_schedule(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+        if st != KS_OK:
+            raise KsError(st, "ks_plan_schedule")
+        return dict(fp32_levels=a.value, fwd_tail_level=b.value, bwd_tail_level=c.value)
 
     def layout(self) -> dict:
         lay = Layout()

@@ -148,3 +148,44 @@ def test_engine_create_errors():
     assert L.ks_engine_create(ctypes.c_void_p((1 << 30) + 8), 64 << 20, None, ctypes.byref(h)) == ks.KS_E_WORKSPACE
     assert L.ks_engine_create(ctypes.c_void_p(1 << 30), 1000, None, ctypes.byref(h)) == ks.KS_E_WORKSPACE
     assert L.ks_engine_create(ctypes.c_void_p(1 << 30), 64 << 20, None, None) == ks.KS_E_ARG
+
+
+def _fake_plan(k, n, m, fp32=False):
+    d = ks.make_desc(k, n, m, True, True, fp32)
+    h = ctypes.c_void_p()
+    nbytes = ks.workspace_bytes(k, n, m, True, True, fp32)
+    assert ks.lib().ks_create(ctypes.byref(d), ctypes.c_void_p(1 << 20), nbytes, None, ctypes.byref(h)) == ks.KS_OK
+    a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    assert ks.lib().ks_plan_schedule(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)) == ks.KS_OK
+    ks.lib().ks_destroy(h)
+    return a.value, b.value, c.value
+
+
+def test_tuning_table_drives_the_schedule(monkeypatch):
+    """The tuning entry of (n, form) decides which top levels run in the tail
+    kernels and which levels run in FP32; the environment overrides it."""
+    monkeypatch.delenv("KS_TAIL_PASSES", raising=False)
+    monkeypatch.delenv("KS_FP32_SWITCH", raising=False)
+    saved = ks.get_tuning(6, False), ks.get_tuning(6, True)
+    try:
+        k, n = 100000, 6
+        L = (k + 1).bit_length() - 1
+        ks.set_tuning(n, False, 0, 0, 1024)
+        assert ks.get_tuning(n, False) == dict(fwd_tail_passes=0, bwd_tail_passes=0, fp32_switch_columns=1024)
+        assert _fake_plan(k, n, 3) == (0, L, L + 1)          # base level only, no backward tail
+        ks.set_tuning(n, False, 10**6, 10**6, 1024)
+        assert _fake_plan(k, n, 3) == (0, 0, 0)              # everything in the tails
+        ks.set_tuning(n, True, 2, 2, 4096)
+        fp32_levels = sum(1 for l in range(L) if (k + 1) >> l > 4096)
+        lev, l0, l1 = _fake_plan(k, n, 3, fp32=True)
+        assert lev == fp32_levels and l0 > lev and l1 >= lev
+        monkeypatch.setenv("KS_TAIL_PASSES", "0")
+        assert _fake_plan(k, n, 3)[1:] == (L, L + 1)
+        with pytest.raises(ks.KsError):
+            ks.set_tuning(0, False, 1, 1, 1024)
+        with pytest.raises(ks.KsError):
+            ks.set_tuning(6, False, -1, 1, 1024)
+    finally:
+        monkeypatch.delenv("KS_TAIL_PASSES", raising=False)
+        for fp32, e in zip((False, True), saved):
+            ks.set_tuning(6, fp32, e["fwd_tail_passes"], e["bwd_tail_passes"], e["fp32_switch_columns"])
