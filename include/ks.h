@@ -126,6 +126,18 @@ ks_status ks_smooth_cov(ks_plan *plan, const double *H, const double *F,
                         const double *o, const double *C, double *u_out,
                         double *cov_out);
 
+/* As ks_smooth_cov, and also the lag-one blocks lag1_out[i] =
+ * cov(u_i, u_{i+1}) = S_{i,i+1}, i = 0..k-1 ([k][n][n], row index over u_i;
+ * may be NULL when k = 0).  Algorithm 2 already forms them at level 0, where
+ * every adjacent pair has its even member: S_{i,i+1} = -P_b and
+ * S_{i-1,i} = -P_a^T for even i (P = R_ii^{-1} R_iI S_II), so exporting them
+ * costs one extra store per block.  Off-diagonal covariance blocks of
+ * Section IV; useful for EM. */
+ks_status ks_smooth_cov_lag1(ks_plan *plan, const double *H, const double *F,
+                             const double *c, const double *K, const double *G,
+                             const double *o, const double *C, double *u_out,
+                             double *cov_out, double *lag1_out);
+
 /* Release the plan's host state (the workspace stays the caller's). */
 ks_status ks_destroy(ks_plan *plan);
 

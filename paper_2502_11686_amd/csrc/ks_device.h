@@ -822,6 +822,16 @@ __device__ __forceinline__ void bwd_unit(const BwdArgs &a, int l, int64_t t, int
 #pragma unroll
                 for (int r = 0; r < N; ++r) dst[r * N + c] = -p[r];
             }
+            // level 0: S_{i,i+1} = -P_b, and S_{i-1,i} = S_{i,i-1}^T = -P_a^T
+            if (l == 0 && a.lag1 && (gl < N ? va : vb)) {
+                if (gl >= N) {
+#pragma unroll
+                    for (int r = 0; r < N; ++r) a.lag1[i * N * N + r * N + (gl - N)] = -p[r];
+                } else {
+#pragma unroll
+                    for (int r = 0; r < N; ++r) a.lag1[(i - 1) * N * N + gl * N + r] = -p[r];
+                }
+            }
         }
         __syncthreads();
         // S_ii = R^{-1} R^{-T} + P T_I^T

@@ -234,6 +234,11 @@ __device__ __forceinline__ void blk_bwd_unit(const BwdArgs &a, int l, int64_t t,
                             double *dst = a.spm + ri * 2 * N * N + (c < N ? 0 : N * N);
                             dst[r * N + (c < N ? c : c - N)] = -acc[u][j];
                         }
+                        // level 0: S_{i,i+1} = -P_b, and S_{i-1,i} = S_{i,i-1}^T = -P_a^T
+                        if (l == 0 && a.lag1 && (c < N ? va : vb)) {
+                            if (c >= N) a.lag1[i * N * N + r * N + (c - N)] = -acc[u][j];
+                            else a.lag1[(i - 1) * N * N + c * N + r] = -acc[u][j];
+                        }
                     }
                 }
             }

@@ -64,6 +64,7 @@ struct BwdArgs {
     double *u_out;
     double *cov;              // cov_out (neighbour blocks are read from it too)
     double *spm;              // S_{i,i-2^l}, S_{i,i+2^l} of records >= spm_first
+    double *lag1;             // level 0 writes S_{i,i+1} = cov(u_i, u_{i+1}) here when non-null
     int64_t spm_first;
     int64_t rec_off[kMaxLevels];
     int64_t Nl[kMaxLevels];

@@ -260,7 +260,7 @@ void enqueue_forward(ks_plan *p, const double *H, const double *F, const double 
     mark(p, KS_TIME_FWD_ALL, 1);
 }
 
-void enqueue_backward(ks_plan *p, double *u_out, double *cov_out) {
+void enqueue_backward(ks_plan *p, double *u_out, double *cov_out, double *lag1_out = nullptr) {
     const Layout &lo = p->lo;
     const int mode = (u_out && cov_out) ? ks::BWD_BOTH : (u_out ? ks::BWD_Y : ks::BWD_COV);
     ks::BwdArgs b{};
@@ -270,6 +270,7 @@ void enqueue_backward(ks_plan *p, double *u_out, double *cov_out) {
     b.u_out = u_out;
     b.cov = cov_out;
     b.spm = seg_d(p, lo.off_spm);
+    b.lag1 = cov_out ? lag1_out : nullptr;
     b.spm_first = lo.spm_first;
     b.store_s = cov_out != nullptr;
     for (int l = 0; l <= lo.L; ++l) {
@@ -388,6 +389,19 @@ ks_status ks_smooth_cov(ks_plan *p, const double *H, const double *F, const doub
     p->smoothed = false;
     enqueue_forward(p, H, F, c, K, G, o, C);
     enqueue_backward(p, u_out, cov_out);
+    ks_status s = finish(p);
+    p->smoothed = s == KS_OK;
+    return s;
+}
+
+ks_status ks_smooth_cov_lag1(ks_plan *p, const double *H, const double *F, const double *c,
+                             const double *K, const double *G, const double *o, const double *C,
+                             double *u_out, double *cov_out, double *lag1_out) {
+    if (!p || !u_out || !cov_out || (!lag1_out && p->d.k > 0) || !inputs_ok(p, F, c, K, G, o, C))
+        return KS_E_ARG;
+    p->smoothed = false;
+    enqueue_forward(p, H, F, c, K, G, o, C);
+    enqueue_backward(p, u_out, cov_out, lag1_out);
     ks_status s = finish(p);
     p->smoothed = s == KS_OK;
     return s;

@@ -28,7 +28,7 @@ SYMBOLS = ("ks_workspace_bytes", "ks_supported", "ks_create", "ks_smooth", "ks_c
            "ks_time_kernels", "ks_kernel_time", "ks_batch_workspace_bytes", "ks_batch_create",
            "ks_batch_smooth", "ks_batch_destroy", "ks_engine_create", "ks_engine_submit",
            "ks_engine_step", "ks_engine_retired", "ks_engine_poll", "ks_engine_query", "ks_engine_destroy",
-           "ks_set_tuning", "ks_get_tuning", "ks_plan_schedule")
+           "ks_set_tuning", "ks_get_tuning", "ks_plan_schedule", "ks_smooth_cov_lag1")
 KS_TIME_OFF, KS_TIME_FWD_LEVEL0, KS_TIME_BWD_LEVEL0, KS_TIME_FWD_ALL, KS_TIME_BWD_ALL = range(5)
 
 
@@ -84,6 +84,8 @@ def lib():
     L.ks_smooth.argtypes = [vp] + [dp] * 8
     L.ks_smooth_cov.restype = ctypes.c_int
     L.ks_smooth_cov.argtypes = [vp] + [dp] * 9
+    L.ks_smooth_cov_lag1.restype = ctypes.c_int
+    L.ks_smooth_cov_lag1.argtypes = [vp] + [dp] * 10
     L.ks_covariances.restype = ctypes.c_int
     L.ks_covariances.argtypes = [vp, dp]
     L.ks_destroy.restype = ctypes.c_int
@@ -290,6 +292,18 @@ class Plan:
         if st != KS_OK:
             raise KsError(st, "ks_smooth_cov")
         return u, cov
+
+    def smooth_cov_lag1(self, H, F, c, K, G, o, C, u_out=None, cov_out=None, lag1_out=None):
+        """States, covariance blocks and the lag-one blocks S_{i,i+1} in one pass."""
+        self._check_inputs(H, F, c, K, G, o, C)
+        u = self._out(u_out, (self.k + 1, self.n), "u_out")
+        cov = self._out(cov_out, (self.k + 1, self.n, self.n), "cov_out")
+        lag1 = self._out(lag1_out, (self.k, self.n, self.n), "lag1_out")
+        st = lib().ks_smooth_cov_lag1(self._h, _ptr(H), _ptr(F), _ptr(c), _ptr(K), _ptr(G), _ptr(o),
+                                      _ptr(C), _ptr(u), _ptr(cov), _ptr(lag1) if self.k > 0 else None)
+        if st != KS_OK:
+            raise KsError(st, "ks_smooth_cov_lag1")
+        return u, cov, lag1
 
     def covariances(self, cov_out=None):
         """Covariance blocks from the R factor of the last successful smooth."""

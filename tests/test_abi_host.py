@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def header_symbols():
     txt = open(os.path.join(ROOT, "include", "ks.h")).read()
-    return sorted(set(re.findall(r"\b(ks_[a-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(ks_[a-z_0-9]+)\s*\(", txt)))
 
 
 def test_exports_every_declared_symbol():
