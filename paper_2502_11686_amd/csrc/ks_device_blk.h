@@ -374,6 +374,6 @@ constexpr KernelSet make_blk_set() {
                      {0, 0, 0}};
 }
 
-#define KS_BLK_SETS(N) make_blk_set<N, (N + 1) / 2>(), make_blk_set<N, N>()
+#define KS_BLK_SETS(N) make_blk_set<N, wg_mm_small(N)>(), make_blk_set<N, N>()
 
 }  // namespace ks

@@ -24,9 +24,13 @@
 
 namespace ks {
 
-// lanes per stack column: 8 where n and the observation class n/2 are
-// multiples of 8 and n >= 32 (more, lighter lanes per unit), else 4
-constexpr int wg_tr(int n) { return (n >= 32 && n % 16 == 0) ? 8 : 4; }
+// lanes per stack column: 8 (more, lighter lanes per unit) where n and the
+// observation classes are multiples of 8, else 4
+constexpr int wg_tr(int n) { return n % 8 == 0 ? 8 : 4; }
+
+// observation classes of the family (padded row counts of a level-0
+// observation block): the smallest multiple of 8 >= n/2, and n
+constexpr int wg_mm_small(int n) { return ((n + 1) / 2 + 7) / 8 * 8; }
 
 template <int N, class T>
 struct WGeo {
