@@ -690,9 +690,9 @@ struct BwdSmem {
     static constexpr int SI = DO_COV ? 4 * N * N : 0;
     static constexpr int TT = N * (2 * N + 1);
     static constexpr int RI = DO_COV ? N * N : 0;
-    static constexpr int PP = DO_COV ? 2 * N * N : 0;
-    static constexpr int SS = DO_COV ? N * N : 0;
-    static constexpr int PER = RR + YI + SI + TT + RI + PP + SS;
+    // P = T_I S_II overwrites the rows of S_II it came from (lane g reads and
+    // writes only column g), S_ii overwrites the R row (dead after the solves)
+    static constexpr int PER = RR + YI + SI + TT + RI;
 };
 
 // One block row of level l (record t): back-substitution and/or the SelInv
@@ -715,8 +715,8 @@ __device__ __forceinline__ void bwd_unit(const BwdArgs &a, int l, int64_t t, int
     double *SII = yI + SM::YI;
     double *TT = SII + SM::SI;
     double *RI = TT + SM::TT;
-    double *PP = RI + SM::RI;
-    double *SS = PP + SM::PP;
+    double *PP = SII;  // rows 0..n-1 of S_II, column by column
+    double *SS = Rr;
 
     // stage the record and the neighbour data (lanes outside a unit skip)
     if (in) {
