@@ -38,7 +38,8 @@ def errs(u, S, ref):
 
 
 @pytest.mark.parametrize("n,m,cov", [(4, 2, "diag"), (6, 3, "dense"), (8, 4, "diag"), (12, 6, "dense"),
-                                     (16, 8, "diag"), (24, 12, "dense"), (32, 16, "diag"), (48, 24, "diag")])
+                                     (16, 8, "diag"), (24, 12, "dense"), (32, 16, "diag"), (48, 24, "diag"),
+                                     (24, 5, "dense"), (32, 32, "dense"), (48, 48, "diag")])
 @pytest.mark.parametrize("switch", [4, 64])
 def test_fp32_form_small_switch(n, m, cov, switch, monkeypatch):
     k = 700 if n <= 16 else 150

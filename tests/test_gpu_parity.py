@@ -42,7 +42,7 @@ def gpu(p, mode="fused"):
 
 SHAPES = [(1, 1), (2, 1), (4, 2), (3, 3), (6, 3), (4, 5), (8, 4), (2, 4), (6, 6), (3, 1), (5, 3),
           (12, 6), (16, 8), (12, 12)]
-LARGE = [(24, 12), (32, 16), (48, 24), (24, 24)]
+LARGE = [(24, 12), (32, 16), (48, 24), (24, 24), (24, 5), (32, 32), (48, 48), (48, 7)]
 KS = list(range(0, 20)) + [31, 32, 33, 63, 64, 100, 127, 128, 129]
 KS_LARGE = [0, 1, 2, 3, 4, 5, 6, 7, 8, 15, 16, 17, 31, 33, 64]
 
