@@ -6,8 +6,9 @@ F_i, dense SPD K_i and C_i, synthetic seeded data already resident in HBM.
 Prints one JSON line:
   value        smoothed time steps per second (k+1 per step / wall time)
   roofline     the level-0 forward kernel (loads raw inputs, whitens, first
-               elimination level): algorithmic bytes per launch / its average
-               duration from hipEvents recorded on its own stream
+               elimination level): algorithmic bytes (below the FP64 ridge
+               point, "hbm") or flops (above it, "alu") per launch / its
+               average duration from hipEvents recorded on its own stream
   cpu_baseline the CPU oracle (sequential FP64 Paige-Saunders + Algorithm 1,
                single thread) timed on this host on a bounded sample
 """
@@ -25,6 +26,8 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# 256 CUs x 4 SIMDs x 16 FP64 lanes x 2 flops per FMA x 2.4 GHz
+FP64_VALU_PEAK_TFS = 78.6
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fwd_level0_n6_k100000.json")
 # sources of the level-0 forward kernel of the benchmark workload (n = 6): a
 # traffic summary taken on other sources is not used
@@ -56,6 +59,39 @@ def level0_forward_bytes(p) -> int:
     return 8 * (reads + writes)
 
 
+def _householder_flops(r: int, c: int, p: int) -> int:
+    """Flops of a Householder QR of an r x c stack whose reflectors are also
+    applied to p further columns: for pivot q (h = r - q rows below and on the
+    diagonal, h > 1) the norm takes 2h and each of the c - q - 1 + p columns to
+    its right a dot product and an update of 2h each (Section II's QR steps)."""
+    f = 0
+    for q in range(min(r, c)):
+        h = r - q
+        if h > 1:
+            f += 2 * h + 4 * h * (c - q - 1 + p)
+    return f
+
+
+def level0_forward_flops(p) -> int:
+    """Algorithmic flops of the level-0 forward launch, from the implemented
+    stack shapes (Section III steps 1-3 with whitening fused in).
+
+    Per unit (even column j and its right neighbour j+1): whitening of two
+    evolution blocks [F | H | c] and two observation blocks [G | o] (Cholesky
+    plus triangular solves for dense covariances, a scaling for diagonal ones);
+    step 1, QR of the (m+n) x n stack [O_j; E-_{j+1}] applied to E+_{j+1} and
+    the right-hand side; step 3, QR of the 2m x n stack [D~_{j+1}; O_{j+1}]
+    with its right-hand side; step 2, QR of the 2n x n stack [E+_j; R~_j]
+    applied to the left neighbour, right neighbour and right-hand side."""
+    k, n, m = p.k, p.n, p.m
+    units = (k + 1) // 2
+    ev = n * (2 * n + 1) if p.K_diag else n ** 3 // 3 + n * n * (2 * n + 1)
+    ob = m * (n + 1) if p.C_diag else m ** 3 // 3 + m * m * (n + 1)
+    per_unit = (2 * ev + 2 * ob + _householder_flops(m + n, n, n + 1) + _householder_flops(2 * m, n, 1)
+                + _householder_flops(2 * n, n, 2 * n + 1))
+    return units * per_unit
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     for f in KERNEL_SRCS:
@@ -71,6 +107,8 @@ def measured_traffic(per_launch_algo: int):
     except (OSError, ValueError):
         return None
     if d.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    if d.get("algorithmic_bytes_per_launch") != per_launch_algo:  # another workload's launch
         return None
     return d.get("bytes_per_launch")
 
@@ -209,8 +247,16 @@ def main():
     plan32.close()
 
     algo = level0_forward_bytes(p)
+    flops = level0_forward_flops(p)
     avg_s = (k_ms / max(k_cnt, 1)) / 1e3
-    achieved = algo / avg_s / 1e9
+    # the bound is the resource the kernel's arithmetic intensity saturates
+    # first: HBM below the FP64 ridge point (peak flops / peak bytes), the FP64
+    # vector units above it (the level kernels do their FP64 arithmetic on VALU)
+    hbm_bound = flops / algo <= FP64_VALU_PEAK_TFS * 1e3 / HBM_PEAK_GBS
+    if hbm_bound:
+        achieved, peak, unit = algo / avg_s / 1e9, HBM_PEAK_GBS, "GB/s"
+    else:
+        achieved, peak, unit = flops / avg_s / 1e12, FP64_VALU_PEAK_TFS, "TFLOP/s"
     traffic = measured_traffic(algo)
     lat_ms = np.array(lat) * 1e3
     out = {
@@ -234,10 +280,12 @@ def main():
         "phase_ms": phases,
         "err_vs_oracle": err,
         "fp32_form": fp32_form,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+        "roofline": {"bound": "hbm" if hbm_bound else "alu", "achieved": achieved, "peak": peak,
+                     "unit": unit, "frac": achieved / peak, "traffic": traffic,
                      "kernel": f"level-0 forward (n={p.n}, m={p.m})", "algo_bytes_per_launch": algo,
-                     "avg_launch_ms": avg_s * 1e3, "launches_timed": k_cnt},
+                     "algo_flops_per_launch": flops, "avg_launch_ms": avg_s * 1e3, "launches_timed": k_cnt,
+                     "hbm_frac": algo / avg_s / 1e9 / HBM_PEAK_GBS,
+                     "fp64_frac": flops / avg_s / 1e12 / FP64_VALU_PEAK_TFS},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p)

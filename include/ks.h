@@ -138,6 +138,25 @@ ks_status ks_smooth_cov_lag1(ks_plan *plan, const double *H, const double *F,
                              const double *o, const double *C, double *u_out,
                              double *cov_out, double *lag1_out);
 
+/* Value of the objective of Section II-A at u: *total = || U (A u - b) ||^2
+ * = sum over i >= 1 of r_i^T K_i^{-1} r_i with r_i = H_i u_i - F_i u_{i-1} - c_i,
+ * plus sum over i >= 0 of s_i^T C_i^{-1} s_i with s_i = G_i u_i - o_i
+ * (dense covariances through their Cholesky factors, read from the lower
+ * triangle).  u is a device array [k+1][n], or NULL for u = 0: then H, F and
+ * G are not read and the value is ||U b||^2, which is the objective at the
+ * current iterate of a Gauss-Newton or Levenberg-Marquardt iteration
+ * (Section II-B) once c and o hold its nonlinear residuals.  terms_out
+ * (device [k+1], may be NULL) receives the per-step terms, evolution and
+ * observation of step i added together.  total is a HOST pointer.  Uses a
+ * small region of the plan's workspace and leaves the R factor of the last
+ * smooth intact.  Synchronizes on the plan's stream.  KS_E_NOT_SPD when some
+ * K_i or C_i has a non-positive pivot; KS_E_NONFINITE when the total is not
+ * finite. */
+ks_status ks_objective(ks_plan *plan, const double *H, const double *F,
+                       const double *c, const double *K, const double *G,
+                       const double *o, const double *C, const double *u,
+                       double *terms_out, double *total);
+
 /* Release the plan's host state (the workspace stays the caller's). */
 ks_status ks_destroy(ks_plan *plan);
 

@@ -86,6 +86,31 @@ def smooth(p):
     return dict(u=u.reshape(k + 1, n), cov=sig, S=S, resid2=resid2)
 
 
+def objective_terms(p, u):
+    """Per-step terms of the objective (A u - b)^T W (A u - b) of Section II-A
+    at u [k+1][n]: for step i, r_i^T K_i^{-1} r_i with the evolution residual
+    r_i = H_i u_i - F_i u_{i-1} - c_i (i >= 1), plus s_i^T C_i^{-1} s_i with the
+    observation residual s_i = G_i u_i - o_i.  W is block diagonal, so the
+    objective is the sum of these terms.  Vectorized over steps (any k)."""
+    k, n, m = p.k, p.n, p.m
+    u = np.asarray(u, dtype=np.float64).reshape(k + 1, n)
+    terms = np.zeros(k + 1)
+    if k > 0:
+        Hu = u[1:] if p.H is None else np.einsum("tij,tj->ti", p.H, u[1:])
+        r = Hu - np.einsum("tij,tj->ti", p.F, u[:-1]) - p.c
+        if p.K_diag:
+            terms[1:] += np.sum(r * r / p.K, axis=1)
+        else:
+            terms[1:] += np.einsum("ti,ti->t", r, np.linalg.solve(p.K, r[..., None])[..., 0])
+    if m:
+        s = np.einsum("tij,tj->ti", p.G, u) - p.o
+        if p.C_diag:
+            terms += np.sum(s * s / p.C, axis=1)
+        else:
+            terms += np.einsum("ti,ti->t", s, np.linalg.solve(p.C, s[..., None])[..., 0])
+    return terms
+
+
 def whitened(p):
     """(U A, U b) with U = L^{-1} for the Cholesky factor cov(e) = L L^T.
 

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
@@ -18,6 +19,7 @@
 
 #include "ks.h"
 #include "ks_internal.h"
+#include "ks_objective.h"
 
 namespace {
 
@@ -34,7 +36,7 @@ struct Layout {
     int64_t nslots;
     int64_t spm_first;                 // first record with stored S blocks (level 1)
     int64_t spm_records;
-    size_t off_rrows, off_sys, off_spm, off_slots, off_flags, total;
+    size_t off_rrows, off_sys, off_spm, off_slots, off_obj, off_flags, total;
 };
 
 bool valid_desc(const ks_desc *d) {
@@ -87,6 +89,8 @@ bool make_layout(const ks_desc *d, const ks::KernelSet *ks_, Layout *lo) {
     off = align_up(off + sizeof(double) * (size_t)lo->spm_records * 2 * n * n);
     lo->off_slots = off;
     off = align_up(off + sizeof(double) * 2 * (size_t)slots);
+    lo->off_obj = off;
+    off = align_up(off + sizeof(double) * (size_t)(ks::kObjBlocks + 1));
     lo->off_flags = off;
     off = align_up(off + 64);
     lo->total = off;
@@ -230,15 +234,16 @@ void enqueue_forward(ks_plan *p, const double *H, const double *F, const double 
         a.fold_slot = a.slots + 2 * blocks;
         // precision of this level: FP32 below the switch, FP64 from it on
         const int v = l < ls ? ks::FV_F32 : (l == ls && l > 0 ? ks::FV_F64_FROM_F32 : ks::FV_F64);
-        if (l == 0) mark(p, KS_TIME_FWD_LEVEL0, 0);
         if (l == 0) {
+            // the level-0 bracket holds the level kernel alone (not the fold)
+            mark(p, KS_TIME_FWD_LEVEL0, 0);
             p->kset->fwd_raw[v == ks::FV_F32](a, p->stream);
+            mark(p, KS_TIME_FWD_LEVEL0, 1);
             if (lo.Nl[l] & 1) p->kset->fold_raw[v == ks::FV_F32](a, p->stream);
         } else {
             p->kset->fwd[v](a, p->stream);
             if (lo.Nl[l] & 1) p->kset->fold[v](a, p->stream);
         }
-        if (l == 0) mark(p, KS_TIME_FWD_LEVEL0, 1);
     }
     ks::FwdTailArgs ta{};
     ta.a = a;
@@ -405,6 +410,44 @@ ks_status ks_smooth_cov_lag1(ks_plan *p, const double *H, const double *F, const
     ks_status s = finish(p);
     p->smoothed = s == KS_OK;
     return s;
+}
+
+ks_status ks_objective(ks_plan *p, const double *H, const double *F, const double *c,
+                       const double *K, const double *G, const double *o, const double *C,
+                       const double *u, double *terms_out, double *total) {
+    if (!p || !total) return KS_E_ARG;
+    const ks_desc &d = p->d;
+    if (d.n > 64 || d.m > 64) return KS_E_ARG;
+    if (d.k > 0 && (!c || !K || (u && !F))) return KS_E_ARG;
+    if (d.m > 0 && (!o || !C || (u && !G))) return KS_E_ARG;
+    ks::ObjArgs a{};
+    a.k = d.k;
+    a.n = d.n;
+    a.m = d.m;
+    a.K_diag = d.K_layout == KS_COV_DIAG;
+    a.C_diag = d.C_layout == KS_COV_DIAG;
+    a.H = u ? H : nullptr;
+    a.F = F; a.c = c; a.K = K; a.G = G; a.o = o; a.C = C;
+    a.u = u;
+    a.terms = terms_out;
+    a.partial = reinterpret_cast<double *>(p->ws + p->lo.off_obj);
+    a.flags = reinterpret_cast<unsigned *>(p->ws + p->lo.off_flags);
+    ks::launch_clear_flags(a.flags, p->stream);
+    ks::launch_objective(a, p->stream);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return KS_E_HIP;
+    double v = 0.0;
+    unsigned f = 0;
+    e = hipMemcpyAsync(&v, a.partial + ks::objective_blocks(d.k), sizeof(double), hipMemcpyDeviceToHost,
+                       p->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&f, a.flags, sizeof(unsigned), hipMemcpyDeviceToHost, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return KS_E_HIP;
+    *total = v;
+    if (f & ks::FLAG_NOT_SPD) return KS_E_NOT_SPD;
+    if (!std::isfinite(v)) return KS_E_NONFINITE;
+    return KS_OK;
 }
 
 ks_status ks_covariances(ks_plan *p, double *cov_out) {

@@ -28,7 +28,7 @@ SYMBOLS = ("ks_workspace_bytes", "ks_supported", "ks_create", "ks_smooth", "ks_c
            "ks_time_kernels", "ks_kernel_time", "ks_batch_workspace_bytes", "ks_batch_create",
            "ks_batch_smooth", "ks_batch_destroy", "ks_engine_create", "ks_engine_submit",
            "ks_engine_step", "ks_engine_retired", "ks_engine_poll", "ks_engine_query", "ks_engine_destroy",
-           "ks_set_tuning", "ks_get_tuning", "ks_plan_schedule", "ks_smooth_cov_lag1")
+           "ks_set_tuning", "ks_get_tuning", "ks_plan_schedule", "ks_smooth_cov_lag1", "ks_objective")
 KS_TIME_OFF, KS_TIME_FWD_LEVEL0, KS_TIME_BWD_LEVEL0, KS_TIME_FWD_ALL, KS_TIME_BWD_ALL = range(5)
 
 
@@ -86,6 +86,8 @@ def lib():
     L.ks_smooth_cov.argtypes = [vp] + [dp] * 9
     L.ks_smooth_cov_lag1.restype = ctypes.c_int
     L.ks_smooth_cov_lag1.argtypes = [vp] + [dp] * 10
+    L.ks_objective.restype = ctypes.c_int
+    L.ks_objective.argtypes = [vp] + [dp] * 9 + [ctypes.POINTER(ctypes.c_double)]
     L.ks_covariances.restype = ctypes.c_int
     L.ks_covariances.argtypes = [vp, dp]
     L.ks_destroy.restype = ctypes.c_int
@@ -304,6 +306,28 @@ class Plan:
         if st != KS_OK:
             raise KsError(st, "ks_smooth_cov_lag1")
         return u, cov, lag1
+
+    def objective(self, H, F, c, K, G, o, C, u=None, terms_out=None) -> float:
+        """||U(Au - b)||^2 at u (None: u = 0, which needs only c, K, o, C);
+        terms_out, if given, receives the per-step terms."""
+        k, n, m, dev = self.k, self.n, self.m, self.device
+        if u is not None:
+            _check(u, "u", (k + 1, n), dev)
+            self._check_inputs(H, F, c, K, G, o, C)
+        else:
+            _check(c, "c", (k, n), dev)
+            _check(K, "K", (k, n) if self.K_diag else (k, n, n), dev)
+            _check(o, "o", (k + 1, m), dev)
+            _check(C, "C", (k + 1, m) if self.C_diag else (k + 1, m, m), dev)
+            H = F = G = None
+        if terms_out is not None:
+            _check(terms_out, "terms_out", (k + 1,), dev)
+        total = ctypes.c_double()
+        st = lib().ks_objective(self._h, _ptr(H), _ptr(F), _ptr(c), _ptr(K), _ptr(G), _ptr(o), _ptr(C),
+                                _ptr(u), _ptr(terms_out), ctypes.byref(total))
+        if st != KS_OK:
+            raise KsError(st, "ks_objective")
+        return total.value
 
     def covariances(self, cov_out=None):
         """Covariance blocks from the R factor of the last successful smooth."""

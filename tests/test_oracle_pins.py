@@ -206,3 +206,36 @@ def test_not_spd():
     p = gen.make_problem(rng, 4, 2, 2, cov="dense")
     p.C[1] = -np.eye(2)
     assert seq.smooth(p, check=False)["status"] == seq.E_NOT_SPD
+
+
+def test_objective_terms_scalar_closed_form():
+    """k = 1, n = m = 1: the objective written out by hand,
+    (g0 u0 - o0)^2/C0 + (h u1 - f u0 - c)^2/K + (g1 u1 - o1)^2/C1."""
+    p = small(31, 1, 1, 1, cov="diag", H_mode="random")
+    u = np.array([[0.7], [-1.3]])
+    h, f, c, K = p.H[0, 0, 0], p.F[0, 0, 0], p.c[0, 0], p.K[0, 0]
+    g0, g1, o0, o1, C0, C1 = p.G[0, 0, 0], p.G[1, 0, 0], p.o[0, 0], p.o[1, 0], p.C[0, 0], p.C[1, 0]
+    t0 = (g0 * 0.7 - o0) ** 2 / C0
+    t1 = (h * -1.3 - f * 0.7 - c) ** 2 / K + (g1 * -1.3 - o1) ** 2 / C1
+    terms = dense.objective_terms(p, u)
+    assert np.allclose(terms, [t0, t1], rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("cov,H_mode", [("diag", "identity"), ("dense", "random")])
+def test_objective_terms_sum_to_assembled_quadratic(cov, H_mode):
+    """The per-step terms add up to (Au - b)^T cov(e)^{-1} (Au - b) of the
+    assembled problem, and at u_hat to its minimum, with
+    J(u_hat + d) - J(u_hat) = d^T A^T W A d for any d."""
+    p = small(32, 9, 3, 2, cov=cov, H_mode=H_mode)
+    rng = np.random.default_rng(5)
+    u = rng.standard_normal((p.k + 1, p.n))
+    A, b, cov_e = dense.assemble(p)
+    r = A @ u.ravel() - b
+    assert np.isclose(dense.objective_terms(p, u).sum(), r @ np.linalg.solve(cov_e, r), rtol=1e-12)
+    ref = dense.smooth(p)
+    J0 = dense.objective_terms(p, ref["u"]).sum()
+    assert np.isclose(J0, ref["resid2"], rtol=1e-10)
+    d = rng.standard_normal(A.shape[1])
+    Ad = A @ d
+    J1 = dense.objective_terms(p, ref["u"] + d.reshape(p.k + 1, p.n)).sum()
+    assert np.isclose(J1 - J0, Ad @ np.linalg.solve(cov_e, Ad), rtol=1e-9)
