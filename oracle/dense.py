@@ -139,3 +139,53 @@ def permuted_R(p, order):
     cols = np.concatenate([np.arange(i * n, (i + 1) * n) for i in order])
     q, r = np.linalg.qr(UA[:, cols])
     return r, q.T @ Ub
+
+
+def assemble_general(gp):
+    """Dense (A, b, cov_e) of a problem with per-step dimensions (Section II-A:
+    u_i in R^{n_i}, H_i l_i x n_i, F_i l_i x n_{i-1}, G_i m_i x n_i), block rows
+    in the order observation 0, evolution 1, observation 1, ..., and block
+    column i at offset n_0 + ... + n_{i-1}."""
+    k = gp.k
+    off = np.concatenate([[0], np.cumsum(gp.n)])
+    N = int(off[-1])
+    rows, rhs, covs = [], [], []
+    for i in range(k + 1):
+        if i >= 1:
+            blk = np.zeros((gp.l[i - 1], N))
+            blk[:, off[i - 1]:off[i]] = -gp.F[i - 1]
+            blk[:, off[i]:off[i + 1]] = gp.H[i - 1]
+            rows.append(blk)
+            rhs.append(gp.c[i - 1])
+            covs.append(gp.K[i - 1])
+        if gp.m[i]:
+            blk = np.zeros((gp.m[i], N))
+            blk[:, off[i]:off[i + 1]] = gp.G[i]
+            rows.append(blk)
+            rhs.append(gp.o[i])
+            covs.append(gp.C[i])
+    A = np.vstack(rows)
+    b = np.concatenate(rhs)
+    cov_e = np.zeros((A.shape[0], A.shape[0]))
+    at = 0
+    for cblk in covs:
+        d = cblk.shape[0]
+        cov_e[at:at + d, at:at + d] = cblk
+        at += d
+    return A, b, cov_e, off
+
+
+def smooth_general(gp):
+    """u_hat_i, Sigma_i = cov(u_hat_i) and the lag-one blocks cov(u_hat_i,
+    u_hat_{i+1}) of a per-step-dimension problem: (A^T W A)^{-1} A^T W b and
+    (A^T W A)^{-1} written out densely (tiny k only)."""
+    A, b, cov_e, off = assemble_general(gp)
+    J = A.T @ np.linalg.solve(cov_e, A)
+    h = A.T @ np.linalg.solve(cov_e, b)
+    S = np.linalg.inv(J)
+    u = np.linalg.solve(J, h)
+    k = gp.k
+    us = [u[off[i]:off[i + 1]] for i in range(k + 1)]
+    cov = [S[off[i]:off[i + 1], off[i]:off[i + 1]] for i in range(k + 1)]
+    lag1 = [S[off[i]:off[i + 1], off[i + 1]:off[i + 2]] for i in range(k)]
+    return dict(u=us, cov=cov, lag1=lag1, J=J)

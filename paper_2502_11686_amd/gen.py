@@ -247,3 +247,60 @@ def request_problem(req: dict) -> Problem:
     rng = np.random.default_rng(req["seed"])
     n = req["n"]
     return make_problem(rng, req["k"], n, n // 2, F_mode="per_step", cov="dense")
+
+
+@dataclass
+class GeneralProblem:
+    """A problem with per-step dimensions (Section II-A): u_i has n[i]
+    components; evolution step i = 1..k has l[i-1] equations with H[i-1]
+    (l x n_i), F[i-1] (l x n_{i-1}), c[i-1], K[i-1] (l x l, dense); state i has
+    m[i] >= 0 observations with G[i] (m_i x n_i), o[i], C[i] (m_i x m_i, dense).
+    Every entry of the lists is a float64 numpy array."""
+    n: list
+    l: list
+    m: list
+    H: list
+    F: list
+    c: list
+    K: list
+    G: list
+    o: list
+    C: list
+
+    @property
+    def k(self) -> int:
+        return len(self.n) - 1
+
+
+def make_general_problem(rng: np.random.Generator, k: int, n_choices=(2, 3, 4, 5),
+                         m_extra: int = 1) -> GeneralProblem:
+    """Random dimensions per step: n_i from n_choices, l_i in n_i - 1 .. n_i + 1
+    (at least 1: H_i rectangular either way, full rank), m_i from
+    max(0, n_i - l_i) to n_i + m_extra (zero allowed when H_i has full column rank),
+    m_0 = n_0; full column rank overall with probability one.  Dense SPD
+    covariances, Haar-based H_i, Gaussian F_i, a simulated trajectory."""
+    n = [int(rng.choice(n_choices)) for _ in range(k + 1)]
+    l, m = [], [n[0]]
+    for i in range(1, k + 1):
+        li = max(1, n[i] + int(rng.integers(-1, 2)))
+        l.append(li)
+        m.append(int(rng.integers(max(0, n[i] - li), n[i] + m_extra + 1)))
+    H, F, c, K, G, o, C = [], [], [], [], [], [], []
+    u = [rng.standard_normal(n[0])]
+    for i in range(1, k + 1):
+        li, ni, np_ = l[i - 1], n[i], n[i - 1]
+        q = haar_orthogonal(rng, 1, max(li, ni))[0]
+        Hi = q[:li, :ni] * rng.uniform(1.0, 2.0, size=(1, ni))
+        Fi = rng.standard_normal((li, np_)) / np.sqrt(np_) * 0.9
+        Ki = spd_dense(rng, 1, li)[0]
+        # a state and the forcing c_i that make the evolution rows hold up to noise
+        ui = rng.standard_normal(ni)
+        ci = Hi @ ui - Fi @ u[-1] - np.linalg.cholesky(Ki) @ rng.standard_normal(li)
+        H.append(Hi); F.append(Fi); c.append(ci); K.append(Ki); u.append(ui)
+    for i in range(k + 1):
+        mi, ni = m[i], n[i]
+        Gi = rng.standard_normal((mi, ni)) / np.sqrt(ni)
+        Ci = spd_dense(rng, 1, mi)[0] if mi else np.zeros((0, 0))
+        noise = np.linalg.cholesky(Ci) @ rng.standard_normal(mi) if mi else np.zeros(0)
+        G.append(Gi); C.append(Ci); o.append(Gi @ u[i] + noise)
+    return GeneralProblem(n=n, l=l, m=m, H=H, F=F, c=c, K=K, G=G, o=o, C=C)

@@ -239,3 +239,88 @@ def test_objective_terms_sum_to_assembled_quadratic(cov, H_mode):
     Ad = A @ d
     J1 = dense.objective_terms(p, ref["u"] + d.reshape(p.k + 1, p.n)).sum()
     assert np.isclose(J1 - J0, Ad @ np.linalg.solve(cov_e, Ad), rtol=1e-9)
+
+
+def _uniform_as_general(p):
+    n, m, k = p.n, p.m, p.k
+    H = [np.eye(n) if p.H is None else p.H[t] for t in range(k)]
+    K = [np.diag(p.K[t]) if p.K_diag else p.K[t] for t in range(k)]
+    C = [np.diag(p.C[i]) if p.C_diag else p.C[i] for i in range(k + 1)]
+    return gen.GeneralProblem(n=[n] * (k + 1), l=[n] * k, m=[m] * (k + 1), H=H, F=list(p.F), c=list(p.c),
+                              K=K, G=list(p.G), o=list(p.o), C=C)
+
+
+def test_general_oracle_reduces_to_uniform():
+    p = small(41, 7, 3, 2, cov="dense", H_mode="random")
+    ref = dense.smooth(p)
+    g = dense.smooth_general(_uniform_as_general(p))
+    assert np.allclose(np.stack(g["u"]), ref["u"], rtol=0, atol=1e-12 * np.abs(ref["u"]).max())
+    assert np.allclose(np.stack(g["cov"]), ref["cov"], rtol=1e-10, atol=1e-14)
+
+
+def _objective_per_step(gp, us):
+    """sum_i r_i^T K_i^{-1} r_i + s_i^T C_i^{-1} s_i, written step by step."""
+    J = 0.0
+    for i in range(gp.k + 1):
+        if i >= 1:
+            r = gp.H[i - 1] @ us[i] - gp.F[i - 1] @ us[i - 1] - gp.c[i - 1]
+            J += r @ np.linalg.solve(gp.K[i - 1], r)
+        if gp.m[i]:
+            s = gp.G[i] @ us[i] - gp.o[i]
+            J += s @ np.linalg.solve(gp.C[i], s)
+    return J
+
+
+def test_general_oracle_against_per_step_objective():
+    """u_hat zeroes the gradient of the objective written per step, and
+    Sigma = (Hessian / 2)^{-1}, both by central differences (the objective is
+    quadratic, so second differences are exact up to rounding)."""
+    gp = gen.make_general_problem(np.random.default_rng(42), 5)
+    ref = dense.smooth_general(gp)
+    off = np.concatenate([[0], np.cumsum(gp.n)])
+    N = int(off[-1])
+    x0 = np.concatenate(ref["u"])
+
+    def f(x):
+        return _objective_per_step(gp, [x[off[i]:off[i + 1]] for i in range(gp.k + 1)])
+
+    h = 1e-3
+    E = np.eye(N) * h
+    grad = np.array([(f(x0 + E[a]) - f(x0 - E[a])) / (2 * h) for a in range(N)])
+    assert np.abs(grad).max() < 1e-6 * max(1.0, f(x0))
+    Hs = np.empty((N, N))
+    for a in range(N):
+        for b in range(N):
+            Hs[a, b] = (f(x0 + E[a] + E[b]) - f(x0 + E[a] - E[b]) - f(x0 - E[a] + E[b]) + f(x0 - E[a] - E[b])) / (4 * h * h)
+    S = np.linalg.inv(Hs / 2)
+    for i in range(gp.k + 1):
+        blk = S[off[i]:off[i + 1], off[i]:off[i + 1]]
+        assert np.allclose(ref["cov"][i], blk, rtol=1e-5, atol=1e-7 * np.abs(blk).max())
+    for i in range(gp.k):
+        blk = S[off[i]:off[i + 1], off[i + 1]:off[i + 2]]
+        assert np.allclose(ref["lag1"][i], blk, rtol=1e-5, atol=1e-6 * np.abs(S).max())
+
+
+def test_general_oracle_unobserved_step_is_the_infinite_variance_limit():
+    """m_i = 0 equals observing u_i with a variance going to infinity."""
+    gp = gen.make_general_problem(np.random.default_rng(43), 6)
+    i = 3  # unobserved, with an evolution block of full column rank (l_i = n_i + 1)
+    rng = np.random.default_rng(1)
+    li = gp.n[i] + 1
+    gp.l[i - 1] = li
+    gp.H[i - 1] = rng.standard_normal((li, gp.n[i]))
+    gp.F[i - 1] = rng.standard_normal((li, gp.n[i - 1]))
+    gp.c[i - 1] = rng.standard_normal(li)
+    gp.K[i - 1] = np.eye(li)
+    gp.m[i], gp.G[i], gp.o[i], gp.C[i] = 0, np.zeros((0, gp.n[i])), np.zeros(0), np.zeros((0, 0))
+    ref = dense.smooth_general(gp)
+    rng = np.random.default_rng(2)
+    big = gen.GeneralProblem(**{f: list(getattr(gp, f)) for f in ("n", "l", "m", "H", "F", "c", "K", "G", "o", "C")})
+    big.m[i] = 2
+    big.G[i] = rng.standard_normal((2, gp.n[i]))
+    big.o[i] = rng.standard_normal(2)
+    big.C[i] = 1e14 * np.eye(2)
+    lim = dense.smooth_general(big)
+    for t in range(gp.k + 1):
+        assert np.allclose(lim["u"][t], ref["u"][t], rtol=0, atol=1e-8 * max(1.0, np.abs(ref["u"][t]).max()))
+        assert np.allclose(lim["cov"][t], ref["cov"][t], rtol=1e-8, atol=1e-10)
