@@ -24,6 +24,7 @@
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr int kMaxSideStreams = 8;  // concurrent kernel classes of a batch
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -617,6 +618,12 @@ struct ks_batch {
     bool have_exec;
     bool use_graph;
     std::vector<unsigned> host_flags;
+    // one side stream per kernel class: the classes share no data, so their
+    // launch sequences run concurrently (forked from and joined back into the
+    // caller's stream; a captured graph gets one branch per class)
+    int nside;
+    hipStream_t side[kMaxSideStreams];
+    hipEvent_t ev_fork, ev_join[kMaxSideStreams];
 };
 
 namespace {
@@ -827,26 +834,43 @@ void enqueue_batch(ks_batch *b, bool cov) {
     const int32_t *mi = dptr<int32_t>(b, b->off_item);
     const int64_t *mb = dptr<int64_t>(b, b->off_blk);
     const int32_t *ml = dptr<int32_t>(b, b->off_level);
+    // kernel classes in order of first appearance, each on its own side stream
+    std::vector<const ks::KernelSet *> classes;
+    for (const BLaunch &L : b->launches[cov])
+        if (std::find(classes.begin(), classes.end(), L.kset) == classes.end()) classes.push_back(L.kset);
+    const bool fork = b->nside > 0 && classes.size() > 1;
+    if (fork) {
+        (void)hipEventRecord(b->ev_fork, b->stream);
+        for (int c = 0; c < b->nside; ++c) (void)hipStreamWaitEvent(b->side[c], b->ev_fork, 0);
+    }
     for (const BLaunch &L : b->launches[cov]) {
         const ks::BlockMap bm{mi + L.map0, mb + L.map0, ml + L.map0};
+        const int cls = (int)(std::find(classes.begin(), classes.end(), L.kset) - classes.begin());
+        hipStream_t st = fork ? b->side[cls % b->nside] : b->stream;
         switch (L.kind) {
         case BLaunch::FWD:
-            if (L.raw) L.kset->fwd_raw_b[L.variant == ks::FV_F32](ft, bm, L.blocks, b->stream);
-            else L.kset->fwd_b[L.variant](ft, bm, L.blocks, b->stream);
+            if (L.raw) L.kset->fwd_raw_b[L.variant == ks::FV_F32](ft, bm, L.blocks, st);
+            else L.kset->fwd_b[L.variant](ft, bm, L.blocks, st);
             break;
         case BLaunch::FOLD:
-            if (L.raw) L.kset->fold_raw_b[L.variant == ks::FV_F32](ft, bm, L.blocks, b->stream);
-            else L.kset->fold_b[L.variant](ft, bm, L.blocks, b->stream);
+            if (L.raw) L.kset->fold_raw_b[L.variant == ks::FV_F32](ft, bm, L.blocks, st);
+            else L.kset->fold_b[L.variant](ft, bm, L.blocks, st);
             break;
         case BLaunch::FTAIL:
-            (L.raw ? L.kset->fwd_tail_raw_b : L.kset->fwd_tail_b)(tt, bm, L.blocks, b->stream);
+            (L.raw ? L.kset->fwd_tail_raw_b : L.kset->fwd_tail_b)(tt, bm, L.blocks, st);
             break;
         case BLaunch::BTAIL:
-            L.kset->bwd_tail_b[mode](bt, bm, L.blocks, b->stream);
+            L.kset->bwd_tail_b[mode](bt, bm, L.blocks, st);
             break;
         case BLaunch::BWD:
-            L.kset->bwd_b[mode][L.variant](bt, bm, L.blocks, b->stream);
+            L.kset->bwd_b[mode][L.variant](bt, bm, L.blocks, st);
             break;
+        }
+    }
+    if (fork) {
+        for (int c = 0; c < b->nside; ++c) {
+            (void)hipEventRecord(b->ev_join[c], b->side[c]);
+            (void)hipStreamWaitEvent(b->stream, b->ev_join[c], 0);
         }
     }
 }
@@ -929,6 +953,24 @@ ks_status ks_batch_create(int32_t count, const ks_desc *descs, void *workspace, 
     b->have_exec = false;
     b->use_graph = !(std::getenv("KS_NO_GRAPH") && std::atoi(std::getenv("KS_NO_GRAPH")) != 0);
     b->host_flags.assign(count, 0u);
+    b->nside = 0;
+    {
+        int want = 4;
+        if (const char *e = std::getenv("KS_BATCH_STREAMS")) want = std::atoi(e);
+        want = std::max(0, std::min(want, kMaxSideStreams));
+        if (want > 0 && hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) == hipSuccess) {
+            for (int c = 0; c < want; ++c) {
+                if (hipStreamCreateWithFlags(&b->side[c], hipStreamNonBlocking) != hipSuccess) break;
+                if (hipEventCreateWithFlags(&b->ev_join[c], hipEventDisableTiming) != hipSuccess) {
+                    (void)hipStreamDestroy(b->side[c]);
+                    break;
+                }
+                b->nside = c + 1;
+            }
+            if (b->nside == 0) (void)hipEventDestroy(b->ev_fork);
+        }
+        (void)hipGetLastError();
+    }
     *out = b;
     return KS_OK;
 }
@@ -990,6 +1032,14 @@ ks_status ks_batch_smooth(ks_batch *b, const ks_io *io, int32_t want_cov, ks_sta
 ks_status ks_batch_destroy(ks_batch *b) {
     if (!b) return KS_E_ARG;
     if (b->have_exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->nside > 0) {
+        (void)hipStreamSynchronize(b->stream);
+        for (int c = 0; c < b->nside; ++c) {
+            (void)hipStreamDestroy(b->side[c]);
+            (void)hipEventDestroy(b->ev_join[c]);
+        }
+        (void)hipEventDestroy(b->ev_fork);
+    }
     delete b;
     return KS_OK;
 }
