@@ -24,7 +24,56 @@
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kMaxSideStreams = 8;  // concurrent kernel classes of a batch
+constexpr int kMaxSideStreams = 8;
+
+// Side streams (default priority) that independent launch sequences are forked
+// onto from the caller's stream and joined back from, by events; under stream
+// capture each side stream becomes one branch of the graph.  KS_SIDE_STREAMS
+// sets their number (0: everything stays on the caller's stream).
+struct SideStreams {
+    int n = 0;
+    hipStream_t s[kMaxSideStreams];
+    hipEvent_t fork_ev, join_ev[kMaxSideStreams];
+
+    void create() {
+        int want = 4;
+        if (const char *e = std::getenv("KS_SIDE_STREAMS")) want = std::atoi(e);
+        want = std::max(0, std::min(want, kMaxSideStreams));
+        n = 0;
+        if (want > 0 && hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming) == hipSuccess) {
+            for (int c = 0; c < want; ++c) {
+                if (hipStreamCreateWithFlags(&s[c], hipStreamNonBlocking) != hipSuccess) break;
+                if (hipEventCreateWithFlags(&join_ev[c], hipEventDisableTiming) != hipSuccess) {
+                    (void)hipStreamDestroy(s[c]);
+                    break;
+                }
+                n = c + 1;
+            }
+            if (n == 0) (void)hipEventDestroy(fork_ev);
+        }
+        (void)hipGetLastError();
+    }
+    void destroy(hipStream_t origin) {
+        if (n == 0) return;
+        (void)hipStreamSynchronize(origin);
+        for (int c = 0; c < n; ++c) {
+            (void)hipStreamDestroy(s[c]);
+            (void)hipEventDestroy(join_ev[c]);
+        }
+        (void)hipEventDestroy(fork_ev);
+        n = 0;
+    }
+    void fork(hipStream_t origin) {
+        (void)hipEventRecord(fork_ev, origin);
+        for (int c = 0; c < n; ++c) (void)hipStreamWaitEvent(s[c], fork_ev, 0);
+    }
+    void join(hipStream_t origin) {
+        for (int c = 0; c < n; ++c) {
+            (void)hipEventRecord(join_ev[c], s[c]);
+            (void)hipStreamWaitEvent(origin, join_ev[c], 0);
+        }
+    }
+};
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -618,12 +667,10 @@ struct ks_batch {
     bool have_exec;
     bool use_graph;
     std::vector<unsigned> host_flags;
-    // one side stream per kernel class: the classes share no data, so their
-    // launch sequences run concurrently (forked from and joined back into the
-    // caller's stream; a captured graph gets one branch per class)
-    int nside;
-    hipStream_t side[kMaxSideStreams];
-    hipEvent_t ev_fork, ev_join[kMaxSideStreams];
+    // kernel classes share no data, so their launch sequences run
+    // concurrently, one side stream per class (a captured graph gets one
+    // branch per class)
+    SideStreams side;
 };
 
 namespace {
@@ -838,15 +885,12 @@ void enqueue_batch(ks_batch *b, bool cov) {
     std::vector<const ks::KernelSet *> classes;
     for (const BLaunch &L : b->launches[cov])
         if (std::find(classes.begin(), classes.end(), L.kset) == classes.end()) classes.push_back(L.kset);
-    const bool fork = b->nside > 0 && classes.size() > 1;
-    if (fork) {
-        (void)hipEventRecord(b->ev_fork, b->stream);
-        for (int c = 0; c < b->nside; ++c) (void)hipStreamWaitEvent(b->side[c], b->ev_fork, 0);
-    }
+    const bool fork = b->side.n > 0 && classes.size() > 1;
+    if (fork) b->side.fork(b->stream);
     for (const BLaunch &L : b->launches[cov]) {
         const ks::BlockMap bm{mi + L.map0, mb + L.map0, ml + L.map0};
         const int cls = (int)(std::find(classes.begin(), classes.end(), L.kset) - classes.begin());
-        hipStream_t st = fork ? b->side[cls % b->nside] : b->stream;
+        hipStream_t st = fork ? b->side.s[cls % b->side.n] : b->stream;
         switch (L.kind) {
         case BLaunch::FWD:
             if (L.raw) L.kset->fwd_raw_b[L.variant == ks::FV_F32](ft, bm, L.blocks, st);
@@ -867,12 +911,7 @@ void enqueue_batch(ks_batch *b, bool cov) {
             break;
         }
     }
-    if (fork) {
-        for (int c = 0; c < b->nside; ++c) {
-            (void)hipEventRecord(b->ev_join[c], b->side[c]);
-            (void)hipStreamWaitEvent(b->stream, b->ev_join[c], 0);
-        }
-    }
+    if (fork) b->side.join(b->stream);
 }
 
 bool same_io(const std::vector<ks_io> &a, const ks_io *io, int n) {
@@ -953,24 +992,7 @@ ks_status ks_batch_create(int32_t count, const ks_desc *descs, void *workspace, 
     b->have_exec = false;
     b->use_graph = !(std::getenv("KS_NO_GRAPH") && std::atoi(std::getenv("KS_NO_GRAPH")) != 0);
     b->host_flags.assign(count, 0u);
-    b->nside = 0;
-    {
-        int want = 4;
-        if (const char *e = std::getenv("KS_BATCH_STREAMS")) want = std::atoi(e);
-        want = std::max(0, std::min(want, kMaxSideStreams));
-        if (want > 0 && hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) == hipSuccess) {
-            for (int c = 0; c < want; ++c) {
-                if (hipStreamCreateWithFlags(&b->side[c], hipStreamNonBlocking) != hipSuccess) break;
-                if (hipEventCreateWithFlags(&b->ev_join[c], hipEventDisableTiming) != hipSuccess) {
-                    (void)hipStreamDestroy(b->side[c]);
-                    break;
-                }
-                b->nside = c + 1;
-            }
-            if (b->nside == 0) (void)hipEventDestroy(b->ev_fork);
-        }
-        (void)hipGetLastError();
-    }
+    b->side.create();
     *out = b;
     return KS_OK;
 }
@@ -1032,14 +1054,7 @@ ks_status ks_batch_smooth(ks_batch *b, const ks_io *io, int32_t want_cov, ks_sta
 ks_status ks_batch_destroy(ks_batch *b) {
     if (!b) return KS_E_ARG;
     if (b->have_exec) (void)hipGraphExecDestroy(b->exec);
-    if (b->nside > 0) {
-        (void)hipStreamSynchronize(b->stream);
-        for (int c = 0; c < b->nside; ++c) {
-            (void)hipStreamDestroy(b->side[c]);
-            (void)hipEventDestroy(b->ev_join[c]);
-        }
-        (void)hipEventDestroy(b->ev_fork);
-    }
+    b->side.destroy(b->stream);
     delete b;
     return KS_OK;
 }
@@ -1096,6 +1111,7 @@ struct ks_engine {
     uint64_t next_ticket, ticks;
     std::vector<char> staging;
     std::vector<unsigned> hflags;
+    SideStreams side;      // the launch groups of one tick are independent
 };
 
 namespace {
@@ -1272,6 +1288,7 @@ ks_status ks_engine_create(void *workspace, size_t ws_bytes, void *hip_stream, k
     e->next_ticket = 1;
     e->ticks = 0;
     e->hflags.assign(kEngSlots, 0u);
+    e->side.create();
     *out = e;
     return KS_OK;
 }
@@ -1430,28 +1447,37 @@ ks_status ks_engine_step(ks_engine *e, int32_t *finished) {
     const int32_t *mi = reinterpret_cast<const int32_t *>(dt + o_i);
     const int64_t *mb = reinterpret_cast<const int64_t *>(dt + o_k);
     const int32_t *ml = reinterpret_cast<const int32_t *>(dt + o_l);
+    // every launch of a tick covers its own requests, so the launches run
+    // concurrently on the side streams, round robin; a fold stays on the
+    // stream of the level launch it follows
+    const bool fork = e->side.n > 0 && launches.size() > 1;
+    if (fork) e->side.fork(e->stream);
+    int group = -1;
     for (const BLaunch &L : launches) {
         const ks::BlockMap bm{mi + L.map0, mb + L.map0, ml + L.map0};
+        if (L.kind != BLaunch::FOLD) ++group;
+        hipStream_t sm = fork ? e->side.s[group % e->side.n] : e->stream;
         switch (L.kind) {
         case BLaunch::FWD:
-            if (L.raw) L.kset->fwd_raw_b[L.variant == ks::FV_F32](ft, bm, L.blocks, e->stream);
-            else L.kset->fwd_b[L.variant](ft, bm, L.blocks, e->stream);
+            if (L.raw) L.kset->fwd_raw_b[L.variant == ks::FV_F32](ft, bm, L.blocks, sm);
+            else L.kset->fwd_b[L.variant](ft, bm, L.blocks, sm);
             break;
         case BLaunch::FOLD:
-            if (L.raw) L.kset->fold_raw_b[L.variant == ks::FV_F32](ft, bm, L.blocks, e->stream);
-            else L.kset->fold_b[L.variant](ft, bm, L.blocks, e->stream);
+            if (L.raw) L.kset->fold_raw_b[L.variant == ks::FV_F32](ft, bm, L.blocks, sm);
+            else L.kset->fold_b[L.variant](ft, bm, L.blocks, sm);
             break;
         case BLaunch::FTAIL:
-            (L.raw ? L.kset->fwd_tail_raw_b : L.kset->fwd_tail_b)(tt, bm, L.blocks, e->stream);
+            (L.raw ? L.kset->fwd_tail_raw_b : L.kset->fwd_tail_b)(tt, bm, L.blocks, sm);
             break;
         case BLaunch::BTAIL:
-            L.kset->bwd_tail_b[L.variant](bt, bm, L.blocks, e->stream);
+            L.kset->bwd_tail_b[L.variant](bt, bm, L.blocks, sm);
             break;
         case BLaunch::BWD:
-            L.kset->bwd_b[L.variant / 2][L.variant % 2](bt, bm, L.blocks, e->stream);
+            L.kset->bwd_b[L.variant / 2][L.variant % 2](bt, bm, L.blocks, sm);
             break;
         }
     }
+    if (fork) e->side.join(e->stream);
     if (hipGetLastError() != hipSuccess) return KS_E_HIP;
     // advance; read the status words of the requests that finish
     std::vector<char> fin(R, 0);
@@ -1531,6 +1557,7 @@ ks_status ks_engine_query(const ks_engine *e, ks_engine_stats *out) {
 
 ks_status ks_engine_destroy(ks_engine *e) {
     if (!e) return KS_E_ARG;
+    e->side.destroy(e->stream);
     delete e;
     return KS_OK;
 }
