@@ -376,4 +376,38 @@ constexpr KernelSet make_blk_set() {
 
 #define KS_BLK_SETS(N) make_blk_set<N, wg_mm_small(N)>(), make_blk_set<N, N>()
 
+// Wavefront-family forward (register-resident units, no barriers) with the
+// workgroup-family backward (MFMA SelInv).  Both families write and read the
+// same R-record layout [R_ii | R_i,right | rho_i | R_i,left] (FP32 records in
+// the first half of their slot), so the halves combine freely.
+template <int N, int MM>
+constexpr KernelSet make_hyb_set() {
+    KernelSet s = make_set<N, MM>();
+    s.bwd[0][0] = &launch_blk_bwd_t<N, true, false, double>;
+    s.bwd[0][1] = &launch_blk_bwd_t<N, true, false, float>;
+    s.bwd[1][0] = &launch_blk_bwd_t<N, false, true, double>;
+    s.bwd[1][1] = &launch_blk_bwd_t<N, false, true, float>;
+    s.bwd[2][0] = &launch_blk_bwd_t<N, true, true, double>;
+    s.bwd[2][1] = &launch_blk_bwd_t<N, true, true, float>;
+    s.bwd_tail[0] = &launch_blk_bwd_tail_t<N, true, false>;
+    s.bwd_tail[1] = &launch_blk_bwd_tail_t<N, false, true>;
+    s.bwd_tail[2] = &launch_blk_bwd_tail_t<N, true, true>;
+    s.bwd_b[0][0] = &launch_blk_bwd_bt<N, true, false, double>;
+    s.bwd_b[0][1] = &launch_blk_bwd_bt<N, true, false, float>;
+    s.bwd_b[1][0] = &launch_blk_bwd_bt<N, false, true, double>;
+    s.bwd_b[1][1] = &launch_blk_bwd_bt<N, false, true, float>;
+    s.bwd_b[2][0] = &launch_blk_bwd_bt<N, true, true, double>;
+    s.bwd_b[2][1] = &launch_blk_bwd_bt<N, true, true, float>;
+    s.bwd_tail_b[0] = &launch_blk_bwd_tail_bt<N, true, false>;
+    s.bwd_tail_b[1] = &launch_blk_bwd_tail_bt<N, false, true>;
+    s.bwd_tail_b[2] = &launch_blk_bwd_tail_bt<N, true, true>;
+    for (int q = 0; q < 3; ++q) {
+        s.upb_bwd[q] = 1;
+        s.upb_bwd_tail[q] = 0;
+    }
+    return s;
+}
+
+#define KS_HYB_SETS(N) make_hyb_set<N, (N + 1) / 2>(), make_hyb_set<N, N>(), make_hyb_set<N, 2 * N>()
+
 }  // namespace ks
