@@ -183,10 +183,11 @@ __device__ __forceinline__ void blk_bwd_unit(const BwdArgs &a, int l, int64_t t,
     }
     if constexpr (DO_COV) {
         constexpr int TM = (N + 15) / 16;      // row tiles (rows >= n are zero)
-        constexpr int TC = 2 * N / 16;         // column tiles of P
+        constexpr int TC = (2 * N + 15) / 16;  // column tiles of P (columns >= 2n are zero)
         constexpr int QP = (TM * TC + 3) / 4;  // P tiles per wavefront
         constexpr int QS = (TM * TM + 3) / 4;  // S tiles per wavefront
-        static_assert(2 * N % 16 == 0, "n must be a multiple of 8");
+        constexpr int KP = (2 * N + 3) / 4;    // K steps of P (inner index >= 2n is zero)
+        constexpr int KS = (3 * N + 3) / 4;    // K steps of S_ii (inner index >= 3n is zero)
         const int wave = g >> 6, lane = g & 63;
         const int lr = lane & 15, lk = lane >> 4;
         // S_II(d, c) for d, c < 2n (missing neighbours give zero blocks)
@@ -202,7 +203,7 @@ __device__ __forceinline__ void blk_bwd_unit(const BwdArgs &a, int l, int64_t t,
 #pragma unroll
         for (int u = 0; u < QP; ++u) acc[u] = mf_d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll 2
-        for (int kk = 0; kk < 2 * N / 4; ++kk) {
+        for (int kk = 0; kk < KP; ++kk) {
             const int d = 4 * kk + lk;
 #pragma unroll
             for (int u = 0; u < QP; ++u) {
@@ -210,8 +211,10 @@ __device__ __forceinline__ void blk_bwd_unit(const BwdArgs &a, int l, int64_t t,
                 if (q < TM * TC) {
                     const int ti = q % TM, tj = q / TM;
                     const int r = 16 * ti + lr;
-                    const double av = r < N ? TI(r, d) : 0.0;
-                    const double bv = SII(d, 16 * tj + lr);
+                    const int cb = 16 * tj + lr;
+                    const bool dk = (2 * N) % 4 == 0 || d < 2 * N;
+                    const double av = r < N && dk ? TI(r, d) : 0.0;
+                    const double bv = cb < 2 * N && dk ? SII(d, cb) : 0.0;
                     acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc[u], 0, 0, 0);
                 }
             }
@@ -227,7 +230,7 @@ __device__ __forceinline__ void blk_bwd_unit(const BwdArgs &a, int l, int64_t t,
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const int r = 16 * ti + lk + 4 * j;
-                    if (r < N) {
+                    if (r < N && c < 2 * N) {
                         PP[r * LT + c] = acc[u][j];
                         if (valid && store_s) {
                             const int64_t ri = a.rec_off[l] + t - a.spm_first;
@@ -249,8 +252,9 @@ __device__ __forceinline__ void blk_bwd_unit(const BwdArgs &a, int l, int64_t t,
 #pragma unroll
         for (int u = 0; u < QS; ++u) sc[u] = mf_d4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll 2
-        for (int kk = 0; kk < 3 * N / 4; ++kk) {
+        for (int kk = 0; kk < KS; ++kk) {
             const int k = 4 * kk + lk;
+            const bool kin = (3 * N) % 4 == 0 || k < 3 * N;
 #pragma unroll
             for (int u = 0; u < QS; ++u) {
                 const int q = wave + 4 * u;
@@ -258,8 +262,8 @@ __device__ __forceinline__ void blk_bwd_unit(const BwdArgs &a, int l, int64_t t,
                     const int ti = q % TM, tj = q / TM;
                     const int r = 16 * ti + lr, c = 16 * tj + lr;
                     double av = 0.0, bv = 0.0;
-                    if (r < N) av = k < N ? RI[r * LR + k] : PP[r * LT + (k - N)];
-                    if (c < N) bv = k < N ? RI[c * LR + k] : TI(c, k - N);
+                    if (r < N && kin) av = k < N ? RI[r * LR + k] : PP[r * LT + (k - N)];
+                    if (c < N && kin) bv = k < N ? RI[c * LR + k] : TI(c, k - N);
                     sc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, sc[u], 0, 0, 0);
                 }
             }
@@ -377,7 +381,8 @@ constexpr KernelSet make_blk_set() {
 #define KS_BLK_SETS(N) make_blk_set<N, wg_mm_small(N)>(), make_blk_set<N, N>()
 
 // Wavefront-family forward (register-resident units, no barriers) with the
-// workgroup-family backward (MFMA SelInv).  Both families write and read the
+// workgroup-family backward (MFMA SelInv; any n: rows, columns and inner
+// indices beyond the block sizes are zero-padded to the 16 x 16 x 4 tiles).  Both families write and read the
 // same R-record layout [R_ii | R_i,right | rho_i | R_i,left] (FP32 records in
 // the first half of their slot), so the halves combine freely.
 template <int N, int MM>

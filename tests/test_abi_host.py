@@ -166,9 +166,9 @@ def test_tuning_table_drives_the_schedule(monkeypatch):
     kernels and which levels run in FP32; the environment overrides it."""
     monkeypatch.delenv("KS_TAIL_PASSES", raising=False)
     monkeypatch.delenv("KS_FP32_SWITCH", raising=False)
-    saved = ks.get_tuning(6, False), ks.get_tuning(6, True)
+    saved = ks.get_tuning(5, False), ks.get_tuning(5, True)
     try:
-        k, n = 100000, 6
+        k, n = 100000, 5  # a class with the wavefront-family backward tail
         L = (k + 1).bit_length() - 1
         ks.set_tuning(n, False, 0, 0, 1024)
         assert ks.get_tuning(n, False) == dict(fwd_tail_passes=0, bwd_tail_passes=0, fp32_switch_columns=1024)
@@ -184,8 +184,8 @@ def test_tuning_table_drives_the_schedule(monkeypatch):
         with pytest.raises(ks.KsError):
             ks.set_tuning(0, False, 1, 1, 1024)
         with pytest.raises(ks.KsError):
-            ks.set_tuning(6, False, -1, 1, 1024)
+            ks.set_tuning(5, False, -1, 1, 1024)
     finally:
         monkeypatch.delenv("KS_TAIL_PASSES", raising=False)
         for fp32, e in zip((False, True), saved):
-            ks.set_tuning(6, fp32, e["fwd_tail_passes"], e["bwd_tail_passes"], e["fp32_switch_columns"])
+            ks.set_tuning(5, fp32, e["fwd_tail_passes"], e["bwd_tail_passes"], e["fp32_switch_columns"])
