@@ -30,6 +30,12 @@ constexpr int wg_tr(int n) { return n % 8 == 0 ? 8 : 4; }
 
 // observation classes of the family (padded row counts of a level-0
 // observation block): the smallest multiple of 8 >= n/2, and n
+// Minimum wavefronts per SIMD the forward kernel is compiled for.  n = 32
+// needs 130 VGPRs unconstrained (3 wavefronts per SIMD, two 5-wavefront
+// workgroups per CU); at 128 (one spilled register) a fourth wavefront per
+// SIMD fits and three workgroups share a CU.  n = 48 spills heavily under
+// the same constraint and runs unconstrained.
+constexpr int wg_min_waves(int n) { return n == 32 ? 4 : 1; }
 constexpr int wg_mm_small(int n) { return ((n + 1) / 2 + 7) / 8 * 8; }
 
 template <int N, class T>
@@ -595,7 +601,7 @@ __device__ __forceinline__ void wg_fwd_unit(const FwdArgs &a, int64_t t, T *vbuf
 // ------------------------------------------------------------------ kernels
 
 template <int N, int MM, bool RAW, class T, class TIN, bool BATCH>
-__global__ __launch_bounds__(WThreads<N>::NT) void k_wg_forward(FwdArgs a0, const FwdArgs *tab,
+__global__ __launch_bounds__(WThreads<N>::NT) __attribute__((amdgpu_waves_per_eu(wg_min_waves(N)))) void k_wg_forward(FwdArgs a0, const FwdArgs *tab,
                                                                     BlockMap bm) {
     const FwdArgs &a = BATCH ? tab[bm.item[blockIdx.x]] : a0;
     const int64_t blk = BATCH ? bm.blk[blockIdx.x] : (int64_t)blockIdx.x;
