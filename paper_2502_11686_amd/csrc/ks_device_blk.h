@@ -382,9 +382,12 @@ constexpr KernelSet make_blk_set() {
 
 // Wavefront-family forward (register-resident units, no barriers) with the
 // workgroup-family backward (MFMA SelInv; any n: rows, columns and inner
-// indices beyond the block sizes are zero-padded to the 16 x 16 x 4 tiles).  Both families write and read the
-// same R-record layout [R_ii | R_i,right | rho_i | R_i,left] (FP32 records in
-// the first half of their slot), so the halves combine freely.
+// indices beyond the block sizes are zero-padded to the 16 x 16 x 4 tiles).
+// Both families write and read the same R-record layout [R_ii | R_i,right |
+// rho_i | R_i,left] (FP32 records in the first half of their slot), so the
+// halves combine freely.  Every backward mode (states only, covariances only,
+// both) comes from the same family, so the states of a states-only pass are
+// bitwise those of a full pass.
 template <int N, int MM>
 constexpr KernelSet make_hyb_set() {
     KernelSet s = make_set<N, MM>();
