@@ -17,6 +17,11 @@ template <int N>
 struct BGeo {
     static constexpr int W = 3 * N + 1;                    // columns of an R row
     static constexpr int TBB = 256;                        // backward workgroup (four MFMA wavefronts)
+    // records per workgroup: small blocks (one R row fits a wavefront's lanes,
+    // at most two P tiles) take one wavefront per record, larger ones all four
+    static constexpr int RPW = (N <= 12) ? 4 : 1;
+    static constexpr int UT = TBB / RPW;                   // threads per record
+    static constexpr int WPU = UT / 64;                    // wavefronts per record
     static constexpr int RREC = N * (3 * N + 1);
     static constexpr int OREC = N * (N + 1);
     static constexpr int EREC = N * (2 * N + 1);
@@ -52,7 +57,8 @@ struct BSmem {
 //     S_ii = RI RI^T + P T_I^T, both as 16x16x4 FP64 MFMA tiles (rows padded
 //     to a multiple of 16); -P gives the blocks S_i,a S_i,b kept for lower
 //     levels, S_ii is symmetrized on the way out.
-// 256 threads; every thread must call it the same number of times.
+// BGeo<N>::UT threads per record (the record's own LDS region sm); every
+// thread of the workgroup must call it the same number of times.
 template <int N, bool DO_Y, bool DO_COV, class TR>
 __device__ __forceinline__ void blk_bwd_unit(const BwdArgs &a, int l, int64_t t, int64_t units,
                                              bool store_s, double *sm) {
@@ -60,7 +66,8 @@ __device__ __forceinline__ void blk_bwd_unit(const BwdArgs &a, int l, int64_t t,
     using SM = BSmem<N, DO_COV>;
     constexpr int W = BG::W;
     constexpr int LR = SM::LR, LT = SM::LT;
-    constexpr int NT = BG::TBB;
+    constexpr int NT = BG::UT;
+    constexpr int WPU = BG::WPU;
     double *Rd = sm;                 // R_ii; then P; then S_ii
     double *TT = sm + SM::TO;        // [T_b | z | T_a]
     double *RI = sm + SM::RO;
@@ -68,7 +75,7 @@ __device__ __forceinline__ void blk_bwd_unit(const BwdArgs &a, int l, int64_t t,
     double *SB = SA + N * LR;
     double *SX = SB + N * LR;
     double *DI = sm + SM::DO;        // 1 / R_ii(r, r), then y_a, y_b
-    const int g = threadIdx.x;
+    const int g = threadIdx.x % NT;
     const bool valid = t < units;
     const int64_t i = ((2 * t + 1) << l) - 1;
     const int64_t aa = i - ((int64_t)1 << l), bb = i + ((int64_t)1 << l);
@@ -184,8 +191,8 @@ __device__ __forceinline__ void blk_bwd_unit(const BwdArgs &a, int l, int64_t t,
     if constexpr (DO_COV) {
         constexpr int TM = (N + 15) / 16;      // row tiles (rows >= n are zero)
         constexpr int TC = (2 * N + 15) / 16;  // column tiles of P (columns >= 2n are zero)
-        constexpr int QP = (TM * TC + 3) / 4;  // P tiles per wavefront
-        constexpr int QS = (TM * TM + 3) / 4;  // S tiles per wavefront
+        constexpr int QP = (TM * TC + WPU - 1) / WPU;  // P tiles per wavefront
+        constexpr int QS = (TM * TM + WPU - 1) / WPU;  // S tiles per wavefront
         constexpr int KP = (2 * N + 3) / 4;    // K steps of P (inner index >= 2n is zero)
         constexpr int KS = (3 * N + 3) / 4;    // K steps of S_ii (inner index >= 3n is zero)
         const int wave = g >> 6, lane = g & 63;
@@ -198,7 +205,7 @@ __device__ __forceinline__ void blk_bwd_unit(const BwdArgs &a, int l, int64_t t,
         };
         // P = T_I S_II.  MFMA 16x16x4 FP64 operands: lane l holds A(l % 16, l / 16)
         // and B(l / 16, l % 16); the result D(l / 16 + 4 j, l % 16) in element j.
-        // Tile q = ti + TM tj runs on wavefront q % 4.
+        // Tile q = ti + TM tj runs on wavefront q % WPU of the record.
         mf_d4 acc[QP];
 #pragma unroll
         for (int u = 0; u < QP; ++u) acc[u] = mf_d4{0.0, 0.0, 0.0, 0.0};
@@ -207,7 +214,7 @@ __device__ __forceinline__ void blk_bwd_unit(const BwdArgs &a, int l, int64_t t,
             const int d = 4 * kk + lk;
 #pragma unroll
             for (int u = 0; u < QP; ++u) {
-                const int q = wave + 4 * u;
+                const int q = wave + WPU * u;
                 if (q < TM * TC) {
                     const int ti = q % TM, tj = q / TM;
                     const int r = 16 * ti + lr;
@@ -223,7 +230,7 @@ __device__ __forceinline__ void blk_bwd_unit(const BwdArgs &a, int l, int64_t t,
         double *PP = Rd;
 #pragma unroll
         for (int u = 0; u < QP; ++u) {
-            const int q = wave + 4 * u;
+            const int q = wave + WPU * u;
             if (q < TM * TC) {
                 const int ti = q % TM, tj = q / TM;
                 const int c = 16 * tj + lr;
@@ -257,7 +264,7 @@ __device__ __forceinline__ void blk_bwd_unit(const BwdArgs &a, int l, int64_t t,
             const bool kin = (3 * N) % 4 == 0 || k < 3 * N;
 #pragma unroll
             for (int u = 0; u < QS; ++u) {
-                const int q = wave + 4 * u;
+                const int q = wave + WPU * u;
                 if (q < TM * TM) {
                     const int ti = q % TM, tj = q / TM;
                     const int r = 16 * ti + lr, c = 16 * tj + lr;
@@ -272,7 +279,7 @@ __device__ __forceinline__ void blk_bwd_unit(const BwdArgs &a, int l, int64_t t,
         double *SS = Rd;
 #pragma unroll
         for (int u = 0; u < QS; ++u) {
-            const int q = wave + 4 * u;
+            const int q = wave + WPU * u;
             if (q < TM * TM) {
                 const int ti = q % TM, tj = q / TM;
                 const int c = 16 * tj + lr;
@@ -298,21 +305,28 @@ template <int N, bool DO_Y, bool DO_COV, class TR, bool BATCH>
 __global__ __launch_bounds__(BGeo<N>::TBB) void k_blk_backward(BwdArgs a0, const BwdArgs *tab,
                                                                BlockMap bm) {
     const BwdArgs &a = BATCH ? tab[bm.item[blockIdx.x]] : a0;
-    __shared__ double sm[BSmem<N, DO_COV>::PER];
+    using BG = BGeo<N>;
+    constexpr int PER = BSmem<N, DO_COV>::PER;
+    __shared__ double sm[BG::RPW * PER];
     const int l = BATCH ? bm.level[blockIdx.x] : a.level;
     const int64_t blk = BATCH ? bm.blk[blockIdx.x] : (int64_t)blockIdx.x;
-    blk_bwd_unit<N, DO_Y, DO_COV, TR>(a, l, blk, (a.Nl[l] + 1) / 2, a.store_s && l >= 1, sm);
+    const int u = threadIdx.x / BG::UT;
+    blk_bwd_unit<N, DO_Y, DO_COV, TR>(a, l, blk * BG::RPW + u, (a.Nl[l] + 1) / 2, a.store_s && l >= 1,
+                                      sm + u * PER);
 }
 
 template <int N, bool DO_Y, bool DO_COV, bool BATCH>
 __global__ __launch_bounds__(BGeo<N>::TBB) void k_blk_bwd_tail(BwdArgs a0, const BwdArgs *tab,
                                                                BlockMap bm) {
     const BwdArgs &a = BATCH ? tab[bm.item[blockIdx.x]] : a0;
-    __shared__ double sm[BSmem<N, DO_COV>::PER];
+    using BG = BGeo<N>;
+    constexpr int PER = BSmem<N, DO_COV>::PER;
+    __shared__ double sm[BG::RPW * PER];
+    const int u = threadIdx.x / BG::UT;
     for (int l = a.level; l >= a.l_lo; --l) {
         const int64_t units = (a.Nl[l] + 1) / 2;
-        for (int64_t t = 0; t < units; ++t)
-            blk_bwd_unit<N, DO_Y, DO_COV, double>(a, l, t, units, a.store_s && l >= 1, sm);
+        for (int64_t t0 = 0; t0 < units; t0 += BG::RPW)
+            blk_bwd_unit<N, DO_Y, DO_COV, double>(a, l, t0 + u, units, a.store_s && l >= 1, sm + u * PER);
         __threadfence();
         __syncthreads();
     }
@@ -323,7 +337,8 @@ __global__ __launch_bounds__(BGeo<N>::TBB) void k_blk_bwd_tail(BwdArgs a0, const
 template <int N, bool Y, bool COV, class TR>
 static void launch_blk_bwd_t(const BwdArgs &a, hipStream_t s) {
     const int64_t units = (a.Nl[a.level] + 1) / 2;
-    hipLaunchKernelGGL((k_blk_backward<N, Y, COV, TR, false>), dim3((unsigned)units), dim3(BGeo<N>::TBB), 0,
+    const int64_t blocks = (units + BGeo<N>::RPW - 1) / BGeo<N>::RPW;
+    hipLaunchKernelGGL((k_blk_backward<N, Y, COV, TR, false>), dim3((unsigned)blocks), dim3(BGeo<N>::TBB), 0,
                        s, a, nullptr, BlockMap{});
 }
 template <int N, bool Y, bool COV, class TR>
@@ -374,7 +389,7 @@ constexpr KernelSet make_blk_set() {
                       &launch_blk_bwd_tail_bt<N, true, true>},
                      1,
                      1,
-                     {1, 1, 1},
+                     {BGeo<N>::RPW, BGeo<N>::RPW, BGeo<N>::RPW},
                      {0, 0, 0}};
 }
 
@@ -410,7 +425,7 @@ constexpr KernelSet make_hyb_set() {
     s.bwd_tail_b[1] = &launch_blk_bwd_tail_bt<N, false, true>;
     s.bwd_tail_b[2] = &launch_blk_bwd_tail_bt<N, true, true>;
     for (int q = 0; q < 3; ++q) {
-        s.upb_bwd[q] = 1;
+        s.upb_bwd[q] = BGeo<N>::RPW;
         s.upb_bwd_tail[q] = 0;
     }
     return s;
