@@ -17,9 +17,10 @@ template <int N>
 struct BGeo {
     static constexpr int W = 3 * N + 1;                    // columns of an R row
     static constexpr int TBB = 256;                        // backward workgroup (four MFMA wavefronts)
-    // records per workgroup: small blocks (one R row fits a wavefront's lanes,
-    // at most two P tiles) take one wavefront per record, larger ones all four
-    static constexpr int RPW = (N <= 12) ? 4 : 1;
+    // records per workgroup (measured): one wavefront per record up to n = 12
+    // (an R row fits its lanes, at most two P tiles), two up to n = 24, all four
+    // above (n = 32 loses with two: its LDS then allows one workgroup per CU)
+    static constexpr int RPW = (N <= 12) ? 4 : (N <= 24) ? 2 : 1;
     static constexpr int UT = TBB / RPW;                   // threads per record
     static constexpr int WPU = UT / 64;                    // wavefronts per record
     static constexpr int RREC = N * (3 * N + 1);
