@@ -585,7 +585,9 @@ __device__ __forceinline__ void rank_flag(double dmin, double dmax, double tol, 
 }
 
 // one forward level, one unit per G lanes, many workgroups
-template <int N, int MM, bool RAW, class T, class TIN, bool BATCH>
+// With FOLD, the last unit of an odd level also folds the last column in
+// (its statistics join its block's slot; the level's fold slot is set neutral).
+template <int N, int MM, bool RAW, class T, class TIN, bool BATCH, bool FOLD = false>
 __global__ __launch_bounds__(kBlock) void k_forward(FwdArgs a0, const FwdArgs *tab, BlockMap bm) {
     const FwdArgs &a = BATCH ? tab[bm.item[blockIdx.x]] : a0;
     const int64_t blk = BATCH ? bm.blk[blockIdx.x] : (int64_t)blockIdx.x;
@@ -593,11 +595,15 @@ __global__ __launch_bounds__(kBlock) void k_forward(FwdArgs a0, const FwdArgs *t
     bool bad = false, nonfinite = false;
     double dmin = INFINITY, dmax = 0.0;
     const int64_t t = blk * Geo<N>::UPB + g.ui;
-    fwd_unit<N, MM, RAW, false, T, TIN>(a, t, g.in, g.gl, g.gbase, dmin, dmax, bad, nonfinite);
+    fwd_unit<N, MM, RAW, FOLD, T, TIN>(a, t, g.in, g.gl, g.gbase, dmin, dmax, bad, nonfinite);
     block_minmax<kBlock>(dmin, dmax, bad, nonfinite, a.flags);
     if (threadIdx.x == 0) {
         a.slots[2 * blk] = dmin;
         a.slots[2 * blk + 1] = dmax;
+        if (FOLD && (a.Nl & 1) && blk == (a.units - 1) / Geo<N>::UPB) {
+            a.fold_slot[0] = INFINITY;
+            a.fold_slot[1] = 0.0;
+        }
     }
 }
 
@@ -911,6 +917,13 @@ static void launch_fwd_t(const FwdArgs &a, hipStream_t s) {
                        a, nullptr, BlockMap{});
 }
 
+template <int N, int MM, class T, class TIN>
+static void launch_fwd_fold_t(const FwdArgs &a, hipStream_t s) {
+    const int64_t blocks = (a.units + Geo<N>::UPB - 1) / Geo<N>::UPB;
+    hipLaunchKernelGGL((k_forward<N, MM, false, T, TIN, false, true>), dim3((unsigned)blocks), dim3(kBlock), 0,
+                       s, a, nullptr, BlockMap{});
+}
+
 template <int N, int MM, bool RAW, class T, class TIN>
 static void launch_fwd_bt(const FwdArgs *tab, BlockMap bm, int64_t blocks, hipStream_t s) {
     hipLaunchKernelGGL((k_forward<N, MM, RAW, T, TIN, true>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
@@ -1006,7 +1019,9 @@ constexpr KernelSet make_set() {
                      {Geo<N>::UPB, Geo<N>::UPB, Geo<N>::UPB},
                      {(BwdTailBlock<N, true, false>::TB / 64) * Geo<N>::UPW,
                       (BwdTailBlock<N, false, true>::TB / 64) * Geo<N>::UPW,
-                      (BwdTailBlock<N, true, true>::TB / 64) * Geo<N>::UPW}};
+                      (BwdTailBlock<N, true, true>::TB / 64) * Geo<N>::UPW},
+                     {&launch_fwd_fold_t<N, MM, double, double>, &launch_fwd_fold_t<N, MM, float, float>,
+                      &launch_fwd_fold_t<N, MM, double, float>}};
 }
 
 #define KS_SETS(N) make_set<N, (N + 1) / 2>(), make_set<N, N>(), make_set<N, 2 * N>()

@@ -116,6 +116,9 @@ struct KernelSet {
     int upb_fwd_tail;       // units per pass of the forward tail
     int upb_bwd[3];
     int upb_bwd_tail[3];
+    // levels >= 1 with the odd level's fold done by the level kernel's last
+    // unit (no separate fold launch); null where the family has none
+    FwdFn fwd_fold[3];
 };
 
 struct KernelSetList {

@@ -290,6 +290,8 @@ void enqueue_forward(ks_plan *p, const double *H, const double *F, const double 
             p->kset->fwd_raw[v == ks::FV_F32](a, p->stream);
             mark(p, KS_TIME_FWD_LEVEL0, 1);
             if (lo.Nl[l] & 1) p->kset->fold_raw[v == ks::FV_F32](a, p->stream);
+        } else if ((lo.Nl[l] & 1) && p->kset->fwd_fold[v]) {
+            p->kset->fwd_fold[v](a, p->stream);  // the level kernel folds the last column itself
         } else {
             p->kset->fwd[v](a, p->stream);
             if (lo.Nl[l] & 1) p->kset->fold[v](a, p->stream);
