@@ -391,7 +391,9 @@ constexpr KernelSet make_blk_set() {
                      1,
                      1,
                      {BGeo<N>::RPW, BGeo<N>::RPW, BGeo<N>::RPW},
-                     {0, 0, 0}};
+                     {0, 0, 0},
+                     {&launch_wg_fwd_fold_t<N, MM, double, double>, &launch_wg_fwd_fold_t<N, MM, float, float>,
+                      &launch_wg_fwd_fold_t<N, MM, double, float>}};
 }
 
 #define KS_BLK_SETS(N) make_blk_set<N, wg_mm_small(N)>(), make_blk_set<N, N>()

@@ -600,7 +600,10 @@ __device__ __forceinline__ void wg_fwd_unit(const FwdArgs &a, int64_t t, T *vbuf
 
 // ------------------------------------------------------------------ kernels
 
-template <int N, int MM, bool RAW, class T, class TIN, bool BATCH>
+// With FOLD, the last unit of an odd level also folds the last column in
+// (its statistics join its workgroup's slot; the level's fold slot is set
+// neutral).
+template <int N, int MM, bool RAW, class T, class TIN, bool BATCH, bool FOLD = false>
 __global__ __launch_bounds__(WThreads<N>::NT) __attribute__((amdgpu_waves_per_eu(wg_min_waves(N)))) void k_wg_forward(FwdArgs a0, const FwdArgs *tab,
                                                                     BlockMap bm) {
     const FwdArgs &a = BATCH ? tab[bm.item[blockIdx.x]] : a0;
@@ -608,11 +611,15 @@ __global__ __launch_bounds__(WThreads<N>::NT) __attribute__((amdgpu_waves_per_eu
     __shared__ T vbuf[4 * WGeo<N, T>::VB];
     bool bad = false, nonfinite = false;
     double dmin = INFINITY, dmax = 0.0;
-    wg_fwd_unit<N, MM, RAW, false, T, TIN>(a, blk, vbuf, dmin, dmax, bad, nonfinite);
+    wg_fwd_unit<N, MM, RAW, FOLD, T, TIN>(a, blk, vbuf, dmin, dmax, bad, nonfinite);
     block_minmax<WGeo<N, double>::NT>(dmin, dmax, bad, nonfinite, a.flags);
     if (threadIdx.x == 0) {
         a.slots[2 * blk] = dmin;
         a.slots[2 * blk + 1] = dmax;
+        if (FOLD && (a.Nl & 1) && blk == a.units - 1) {
+            a.fold_slot[0] = INFINITY;
+            a.fold_slot[1] = 0.0;
+        }
     }
 }
 
@@ -704,6 +711,11 @@ __global__ __launch_bounds__(WThreads<N>::NT) void k_wg_fwd_tail(FwdTailArgs ta0
 template <int N, int MM, bool RAW, class T, class TIN>
 static void launch_wg_fwd_t(const FwdArgs &a, hipStream_t s) {
     hipLaunchKernelGGL((k_wg_forward<N, MM, RAW, T, TIN, false>), dim3((unsigned)a.units),
+                       dim3(WGeo<N, double>::NT), 0, s, a, nullptr, BlockMap{});
+}
+template <int N, int MM, class T, class TIN>
+static void launch_wg_fwd_fold_t(const FwdArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL((k_wg_forward<N, MM, false, T, TIN, false, true>), dim3((unsigned)a.units),
                        dim3(WGeo<N, double>::NT), 0, s, a, nullptr, BlockMap{});
 }
 template <int N, int MM, bool RAW, class T, class TIN>
