@@ -148,8 +148,9 @@ def main():
     ap.add_argument("--no-check", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(independent problems shard with no communication; see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (independent problems "
+              "would shard with no communication, one long trajectory by time chunks with one exchange of "
+              "the chunk-top reduced columns)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

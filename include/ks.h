@@ -98,7 +98,7 @@ typedef struct ks_plan ks_plan;
  * the description is invalid or unsupported.  Host-only; no GPU needed. */
 size_t ks_workspace_bytes(const ks_desc *desc);
 
-/* Whether this build has kernels for state dimension n and observation
+/* Whether the library has kernels for state dimension n and observation
  * dimension m (1 = yes, 0 = no).  Host-only. */
 int ks_supported(int32_t n, int32_t m);
 
