@@ -149,6 +149,75 @@ bool make_layout(const ks_desc *d, const ks::KernelSet *ks_, Layout *lo) {
 
 }  // namespace
 
+// A captured launch sequence, keyed by the pointers it was captured with
+// (the pointer set also fixes the mode).  KS_NO_GRAPH=1 in the environment
+// turns capture off.
+struct PassGraph {
+    bool enabled = false, have = false;
+    hipStream_t cap = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const void *key[12] = {};
+    int nkey = 0;
+
+    void create() {
+        const char *e = std::getenv("KS_NO_GRAPH");
+        enabled = !(e && std::atoi(e) != 0) &&
+                  hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) == hipSuccess;
+        (void)hipGetLastError();
+    }
+    void drop() {
+        if (have) (void)hipGraphExecDestroy(exec);
+        have = false;
+    }
+    void destroy() {
+        drop();
+        if (cap) (void)hipStreamDestroy(cap);
+        cap = nullptr;
+        enabled = false;
+    }
+    bool same_key(const void *const *k, int n) const {
+        if (n != nkey) return false;
+        for (int i = 0; i < n; ++i)
+            if (k[i] != key[i]) return false;
+        return true;
+    }
+    // Runs enqueue(stream) for `origin`.  A key seen for the first time runs
+    // eagerly (callers whose pointers change every call never pay a capture);
+    // the second consecutive call with the same key captures the sequence on
+    // the private stream, and later ones replay it.
+    template <class F>
+    void run(hipStream_t origin, const void *const *k, int n, F &&enqueue) {
+        if (!enabled) {
+            enqueue(origin);
+            return;
+        }
+        if (!same_key(k, n)) {
+            drop();
+            nkey = n;
+            for (int i = 0; i < n; ++i) key[i] = k[i];
+            enqueue(origin);
+            return;
+        }
+        if (!have) {
+            hipGraph_t g;
+            if (hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+                enqueue(cap);
+                if (hipStreamEndCapture(cap, &g) == hipSuccess) {
+                    if (hipGraphInstantiate(&exec, g, nullptr, nullptr, 0) == hipSuccess) have = true;
+                    (void)hipGraphDestroy(g);
+                }
+            }
+            (void)hipGetLastError();
+            if (!have) enabled = false;  // capture unavailable: stay eager from now on
+        }
+        if (have) {
+            (void)hipGraphLaunch(exec, origin);
+        } else {
+            enqueue(origin);
+        }
+    }
+};
+
 struct ks_plan {
     ks_desc d;
     hipStream_t stream;
@@ -168,6 +237,10 @@ struct ks_plan {
     bool ev_made;
     double time_ms;
     int64_t time_count;
+    // the last call's launch sequence as a graph, replayed while its pointers
+    // and mode repeat (captured on a private stream: capture is not possible
+    // on the legacy default stream a caller may pass)
+    PassGraph graph;
 };
 
 namespace {
@@ -376,6 +449,27 @@ bool inputs_ok(const ks_plan *p, const double *F, const double *c, const double 
     return true;
 }
 
+// One smoothing pass (forward, then the backward for the given outputs) on
+// the plan's stream, as a replayed graph when possible.  Timed calls run
+// eagerly (their event marks bracket individual launches).
+void run_pass(ks_plan *p, const double *H, const double *F, const double *c, const double *K,
+              const double *G, const double *o, const double *C, double *u_out, double *cov_out,
+              double *lag1_out) {
+    auto enqueue = [&](hipStream_t st) {
+        hipStream_t keep = p->stream;
+        p->stream = st;
+        enqueue_forward(p, H, F, c, K, G, o, C);
+        enqueue_backward(p, u_out, cov_out, lag1_out);
+        p->stream = keep;
+    };
+    if (p->time_kind != KS_TIME_OFF) {
+        enqueue(p->stream);
+        return;
+    }
+    const void *key[10] = {H, F, c, K, G, o, C, u_out, cov_out, lag1_out};
+    p->graph.run(p->stream, key, 10, enqueue);
+}
+
 }  // namespace
 
 extern "C" {
@@ -414,6 +508,7 @@ ks_status ks_create(const ks_desc *desc, void *workspace, size_t ws_bytes, void 
     p->time_kind = KS_TIME_OFF;
     p->time_armed = false;
     p->ev_made = false;
+    p->graph.create();
     p->time_ms = 0.0;
     p->time_count = 0;
     for (int mode = 0; mode < 3; ++mode) {
@@ -432,8 +527,7 @@ ks_status ks_smooth(ks_plan *p, const double *H, const double *F, const double *
                     double *u_out) {
     if (!p || !u_out || !inputs_ok(p, F, c, K, G, o, C)) return KS_E_ARG;
     p->smoothed = false;
-    enqueue_forward(p, H, F, c, K, G, o, C);
-    enqueue_backward(p, u_out, nullptr);
+    run_pass(p, H, F, c, K, G, o, C, u_out, nullptr, nullptr);
     ks_status s = finish(p);
     p->smoothed = s == KS_OK;
     return s;
@@ -444,8 +538,7 @@ ks_status ks_smooth_cov(ks_plan *p, const double *H, const double *F, const doub
                         double *u_out, double *cov_out) {
     if (!p || !u_out || !cov_out || !inputs_ok(p, F, c, K, G, o, C)) return KS_E_ARG;
     p->smoothed = false;
-    enqueue_forward(p, H, F, c, K, G, o, C);
-    enqueue_backward(p, u_out, cov_out);
+    run_pass(p, H, F, c, K, G, o, C, u_out, cov_out, nullptr);
     ks_status s = finish(p);
     p->smoothed = s == KS_OK;
     return s;
@@ -457,8 +550,7 @@ ks_status ks_smooth_cov_lag1(ks_plan *p, const double *H, const double *F, const
     if (!p || !u_out || !cov_out || (!lag1_out && p->d.k > 0) || !inputs_ok(p, F, c, K, G, o, C))
         return KS_E_ARG;
     p->smoothed = false;
-    enqueue_forward(p, H, F, c, K, G, o, C);
-    enqueue_backward(p, u_out, cov_out, lag1_out);
+    run_pass(p, H, F, c, K, G, o, C, u_out, cov_out, lag1_out);
     ks_status s = finish(p);
     p->smoothed = s == KS_OK;
     return s;
@@ -516,6 +608,7 @@ ks_status ks_covariances(ks_plan *p, double *cov_out) {
 
 ks_status ks_destroy(ks_plan *p) {
     if (!p) return KS_E_ARG;
+    p->graph.destroy();
     if (p->ev_made) {
         (void)hipEventDestroy(p->ev[0]);
         (void)hipEventDestroy(p->ev[1]);
@@ -669,6 +762,7 @@ struct ks_batch {
     bool have_exec;
     bool use_graph;
     std::vector<unsigned> host_flags;
+    hipStream_t cap;  // private capture stream (capture is impossible on the legacy default stream)
     // kernel classes share no data, so their launch sequences run
     // concurrently, one side stream per class (a captured graph gets one
     // branch per class)
@@ -994,6 +1088,9 @@ ks_status ks_batch_create(int32_t count, const ks_desc *descs, void *workspace, 
     b->have_exec = false;
     b->use_graph = !(std::getenv("KS_NO_GRAPH") && std::atoi(std::getenv("KS_NO_GRAPH")) != 0);
     b->host_flags.assign(count, 0u);
+    b->cap = nullptr;
+    if (b->use_graph && hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) b->cap = nullptr;
+    (void)hipGetLastError();
     b->side.create();
     *out = b;
     return KS_OK;
@@ -1019,15 +1116,18 @@ ks_status ks_batch_smooth(ks_batch *b, const ks_io *io, int32_t want_cov, ks_sta
             (void)hipGraphExecDestroy(b->exec);
             b->have_exec = false;
         }
-        if (b->use_graph) {
+        if (b->use_graph && b->cap) {
             hipGraph_t g;
-            if (hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+            hipStream_t origin = b->stream;
+            b->stream = b->cap;
+            if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) == hipSuccess) {
                 enqueue_batch(b, cov);
-                if (hipStreamEndCapture(b->stream, &g) == hipSuccess) {
+                if (hipStreamEndCapture(b->cap, &g) == hipSuccess) {
                     if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) == hipSuccess) b->have_exec = true;
                     (void)hipGraphDestroy(g);
                 }
             }
+            b->stream = origin;
             (void)hipGetLastError();
         }
     }
@@ -1057,6 +1157,7 @@ ks_status ks_batch_destroy(ks_batch *b) {
     if (!b) return KS_E_ARG;
     if (b->have_exec) (void)hipGraphExecDestroy(b->exec);
     b->side.destroy(b->stream);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
     delete b;
     return KS_OK;
 }

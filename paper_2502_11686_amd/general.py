@@ -46,25 +46,34 @@ def embedding_dims(gp) -> tuple:
 
 
 def embed(gp, n: int, m: int):
-    """Uniform arrays (numpy, dense covariances) of the embedded problem."""
+    """Uniform arrays (numpy, dense covariances) of the embedded problem.  Steps
+    are placed in groups of equal block shapes (one fancy-indexed copy per
+    group, not per step)."""
     k = gp.k
     H = np.zeros((k, n, n)); F = np.zeros((k, n, n)); c = np.zeros((k, n))
     K = np.broadcast_to(np.eye(n), (k, n, n)).copy()
     G = np.zeros((k + 1, m, n)); o = np.zeros((k + 1, m))
     C = np.broadcast_to(np.eye(m), (k + 1, m, m)).copy()
+    groups = {}
     for t in range(k):
-        li, ni, np_ = gp.l[t], gp.n[t + 1], gp.n[t]
-        H[t, :li, :ni] = gp.H[t]
-        F[t, :li, :np_] = gp.F[t]
-        c[t, :li] = gp.c[t]
-        K[t, :li, :li] = gp.K[t]
+        groups.setdefault((gp.l[t], gp.n[t + 1], gp.n[t]), []).append(t)
+    for (li, ni, np_), ts in groups.items():
+        ts = np.asarray(ts)
+        H[ts, :li, :ni] = np.stack([gp.H[t] for t in ts])
+        F[ts, :li, :np_] = np.stack([gp.F[t] for t in ts])
+        c[ts, :li] = np.stack([gp.c[t] for t in ts])
+        K[ts, :li, :li] = np.stack([gp.K[t] for t in ts])
+    groups = {}
     for i in range(k + 1):
-        mi, ni = gp.m[i], gp.n[i]
-        G[i, :mi, :ni] = gp.G[i]
-        o[i, :mi] = gp.o[i]
-        C[i, :mi, :mi] = gp.C[i]
-        pad = n - ni
-        G[i, mi + np.arange(pad), ni + np.arange(pad)] = 1.0
+        groups.setdefault((gp.m[i], gp.n[i]), []).append(i)
+    for (mi, ni), idx in groups.items():
+        idx = np.asarray(idx)
+        if mi:
+            G[idx, :mi, :ni] = np.stack([gp.G[i] for i in idx])
+            o[idx, :mi] = np.stack([gp.o[i] for i in idx])
+            C[idx, :mi, :mi] = np.stack([gp.C[i] for i in idx])
+        pad = np.arange(n - ni)
+        G[idx[:, None], mi + pad[None, :], ni + pad[None, :]] = 1.0
     return H, F, c, K, G, o, C
 
 

@@ -1,0 +1,55 @@
+"""GPU: a plan replays its launch sequence as a graph once the same pointers
+come twice in a row; every replay must equal an eager pass (a plan created
+with KS_NO_GRAPH=1) bit for bit, also after the inputs changed in place and
+with other work and synchronizations between the replays."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2502_11686_amd import gen, ks
+
+pytestmark = pytest.mark.gpu
+
+
+def _eager(p, args, monkeypatch, fn):
+    monkeypatch.setenv("KS_NO_GRAPH", "1")
+    plan = ks.Plan(p.k, p.n, p.m, p.K_diag, p.C_diag)
+    monkeypatch.delenv("KS_NO_GRAPH")
+    try:
+        out = fn(plan, args)
+        torch.cuda.synchronize()
+        return [o.cpu().numpy() for o in out]
+    finally:
+        plan.close()
+
+
+@pytest.mark.parametrize("n,m,k,cov", [(6, 3, 3000, "dense"), (16, 8, 500, "diag"), (48, 24, 60, "diag")])
+def test_plan_graph_replays_equal_eager(n, m, k, cov, monkeypatch):
+    monkeypatch.delenv("KS_NO_GRAPH", raising=False)
+    p = gen.make_problem(np.random.default_rng(n + k), k, n, m, cov=cov)
+    args = list(ks.to_device(p))
+    side = gen.make_problem(np.random.default_rng(1), 200, 4, 2)
+    side_args = ks.to_device(side)
+    plan = ks.Plan(p.k, p.n, p.m, p.K_diag, p.C_diag)
+    other = ks.Plan(side.k, side.n, side.m, side.K_diag, side.C_diag)
+    u = torch.empty((k + 1, n), dtype=torch.float64, device="cuda")
+    S = torch.empty((k + 1, n, n), dtype=torch.float64, device="cuda")
+    try:
+        for call in range(5):
+            if call == 3:
+                args[5].mul_(1.25)  # observations change in place: the replay must read the new values
+            plan.smooth_cov(*args, u_out=u, cov_out=S)
+            got = [u.cpu().numpy(), S.cpu().numpy()]
+            other.smooth_cov(*side_args)  # unrelated eager work between replays
+            torch.cuda.synchronize()
+            ref = _eager(p, args, monkeypatch, lambda pl, a: pl.smooth_cov(*a))
+            assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1]), call
+        # states only with the same u: a new key, then a replay of its own graph
+        for call in range(3):
+            plan.smooth(*args, u_out=u)
+            got = u.cpu().numpy()
+            ref = _eager(p, args, monkeypatch, lambda pl, a: (pl.smooth(*a),))
+            assert np.array_equal(got, ref[0]), call
+    finally:
+        plan.close()
+        other.close()
