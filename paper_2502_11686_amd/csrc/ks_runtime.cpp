@@ -185,19 +185,18 @@ struct PassGraph {
     // eagerly (callers whose pointers change every call never pay a capture);
     // the second consecutive call with the same key captures the sequence on
     // the private stream, and later ones replay it.
-    // Returns whether the sequence ran as a graph.
     template <class F>
-    bool run(hipStream_t origin, const void *const *k, int n, F &&enqueue) {
+    void run(hipStream_t origin, const void *const *k, int n, F &&enqueue) {
         if (!enabled) {
             enqueue(origin);
-            return false;
+            return;
         }
         if (!same_key(k, n)) {
             drop();
             nkey = n;
             for (int i = 0; i < n; ++i) key[i] = k[i];
             enqueue(origin);
-            return false;
+            return;
         }
         if (!have) {
             hipGraph_t g;
@@ -213,10 +212,9 @@ struct PassGraph {
         }
         if (have) {
             (void)hipGraphLaunch(exec, origin);
-            return true;
+        } else {
+            enqueue(origin);
         }
-        enqueue(origin);
-        return false;
     }
 };
 
@@ -243,8 +241,6 @@ struct ks_plan {
     // and mode repeat (captured on a private stream: capture is not possible
     // on the legacy default stream a caller may pass)
     PassGraph graph;
-    bool timed_by_graph;   // this call's timing events are nodes of the replayed graph
-    bool graph_timing_off; // event nodes gave no elapsed time once: timed calls run eagerly
 };
 
 namespace {
@@ -265,11 +261,7 @@ void collect_time(ks_plan *p) {
     if (hipEventElapsedTime(&ms, p->ev[0], p->ev[1]) == hipSuccess) {
         p->time_ms += ms;
         p->time_count += 1;
-    } else if (p->timed_by_graph) {
-        p->graph_timing_off = true;
     }
-    p->timed_by_graph = false;
-    (void)hipGetLastError();
 }
 
 double *seg_d(ks_plan *p, size_t off) { return reinterpret_cast<double *>(p->ws + off); }
@@ -458,9 +450,8 @@ bool inputs_ok(const ks_plan *p, const double *F, const double *c, const double 
 }
 
 // One smoothing pass (forward, then the backward for the given outputs) on
-// the plan's stream, as a replayed graph when possible.  A timed call's event
-// marks are captured with the launches they bracket; if such events ever give
-// no elapsed time, timed calls run eagerly from then on.
+// the plan's stream, as a replayed graph when possible.  Timed calls run
+// eagerly (their event marks bracket individual launches).
 void run_pass(ks_plan *p, const double *H, const double *F, const double *c, const double *K,
               const double *G, const double *o, const double *C, double *u_out, double *cov_out,
               double *lag1_out) {
@@ -471,18 +462,12 @@ void run_pass(ks_plan *p, const double *H, const double *F, const double *c, con
         enqueue_backward(p, u_out, cov_out, lag1_out);
         p->stream = keep;
     };
-    const bool timed = p->time_kind != KS_TIME_OFF;
-    if (timed && p->graph_timing_off) {
+    if (p->time_kind != KS_TIME_OFF) {
         enqueue(p->stream);
         return;
     }
-    // the timing kind is part of the key: its event records are graph nodes
-    const void *key[11] = {H, F, c, K, G, o, C, u_out, cov_out, lag1_out,
-                           reinterpret_cast<const void *>(static_cast<intptr_t>(p->time_kind))};
-    if (p->graph.run(p->stream, key, 11, enqueue) && timed) {
-        p->time_armed = true;  // a replay records the captured events again
-        p->timed_by_graph = true;
-    }
+    const void *key[10] = {H, F, c, K, G, o, C, u_out, cov_out, lag1_out};
+    p->graph.run(p->stream, key, 10, enqueue);
 }
 
 }  // namespace
@@ -524,8 +509,6 @@ ks_status ks_create(const ks_desc *desc, void *workspace, size_t ws_bytes, void 
     p->time_armed = false;
     p->ev_made = false;
     p->graph.create();
-    p->timed_by_graph = false;
-    p->graph_timing_off = false;
     p->time_ms = 0.0;
     p->time_count = 0;
     for (int mode = 0; mode < 3; ++mode) {
