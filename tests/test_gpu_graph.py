@@ -53,3 +53,28 @@ def test_plan_graph_replays_equal_eager(n, m, k, cov, monkeypatch):
     finally:
         plan.close()
         other.close()
+
+
+def test_plan_graph_replays_report_errors_per_call(monkeypatch):
+    """The status words are cleared by a kernel inside the graph: a replayed
+    pass reports KS_E_NOT_SPD while K is broken and KS_OK once K is repaired in
+    place, call by call."""
+    monkeypatch.delenv("KS_NO_GRAPH", raising=False)
+    p = gen.make_problem(np.random.default_rng(21), 300, 4, 2, cov="diag")
+    args = list(ks.to_device(p))
+    plan = ks.Plan(p.k, p.n, p.m, p.K_diag, p.C_diag)
+    u = torch.empty((p.k + 1, p.n), dtype=torch.float64, device="cuda")
+    S = torch.empty((p.k + 1, p.n, p.n), dtype=torch.float64, device="cuda")
+    good = args[3][17, 2].item()
+    try:
+        for call, broken in enumerate([False, True, True, True, False, False, True, False]):
+            args[3][17, 2] = -1.0 if broken else good
+            torch.cuda.synchronize()
+            if broken:
+                with pytest.raises(ks.KsError) as ei:
+                    plan.smooth_cov(*args, u_out=u, cov_out=S)
+                assert ei.value.status == ks.KS_E_NOT_SPD, call
+            else:
+                plan.smooth_cov(*args, u_out=u, cov_out=S)
+    finally:
+        plan.close()
