@@ -325,8 +325,10 @@ Schedule make_schedule(const ks_desc &d, const ks::KernelSet *kset, const Layout
     return sc;
 }
 
+// part 0: the whole forward sweep; 1: its head (status clear and level 0);
+// 2: the rest (levels >= 1 and the tail).  Parts 1 and 2 need l0 >= 2.
 void enqueue_forward(ks_plan *p, const double *H, const double *F, const double *c,
-                     const double *K, const double *G, const double *o, const double *C) {
+                     const double *K, const double *G, const double *o, const double *C, int part = 0) {
     const Layout &lo = p->lo;
     const int64_t n = p->d.n;
     const int64_t rrec = n * (3 * n + 1);
@@ -334,8 +336,10 @@ void enqueue_forward(ks_plan *p, const double *H, const double *F, const double 
     double *sys = seg_d(p, lo.off_sys);
     double *slots = seg_d(p, lo.off_slots);
     unsigned *flags = reinterpret_cast<unsigned *>(p->ws + lo.off_flags);
-    ks::launch_clear_flags(flags, p->stream);
-    mark(p, KS_TIME_FWD_ALL, 0);
+    if (part != 2) {
+        ks::launch_clear_flags(flags, p->stream);
+        mark(p, KS_TIME_FWD_ALL, 0);
+    }
     const int l0 = p->l0;
     const int ls = p->l_switch;
     ks::FwdArgs a{};
@@ -345,7 +349,8 @@ void enqueue_forward(ks_plan *p, const double *H, const double *F, const double 
     a.C_diag = p->d.C_layout == KS_COV_DIAG;
     a.H = H; a.F = F; a.c = c; a.K = K; a.G = G; a.o = o; a.C = C;
     a.flags = flags;
-    for (int l = 0; l < l0; ++l) {
+    const int l_first = part == 2 ? 1 : 0, l_end = part == 1 ? 1 : l0;
+    for (int l = l_first; l < l_end; ++l) {
         a.Nl = lo.Nl[l];
         a.units = lo.Nl[l] / 2;
         a.level = l;
@@ -370,6 +375,7 @@ void enqueue_forward(ks_plan *p, const double *H, const double *F, const double 
             if (lo.Nl[l] & 1) p->kset->fold[v](a, p->stream);
         }
     }
+    if (part == 1) return;
     ks::FwdTailArgs ta{};
     ta.a = a;
     ta.l0 = l0;
@@ -451,7 +457,8 @@ bool inputs_ok(const ks_plan *p, const double *F, const double *c, const double 
 
 // One smoothing pass (forward, then the backward for the given outputs) on
 // the plan's stream, as a replayed graph when possible.  Timed calls run
-// eagerly (their event marks bracket individual launches).
+// eagerly (their event marks bracket individual launches), except that a call
+// timing the level-0 launch replays everything after level 0.
 void run_pass(ks_plan *p, const double *H, const double *F, const double *c, const double *K,
               const double *G, const double *o, const double *C, double *u_out, double *cov_out,
               double *lag1_out) {
@@ -462,6 +469,21 @@ void run_pass(ks_plan *p, const double *H, const double *F, const double *c, con
         enqueue_backward(p, u_out, cov_out, lag1_out);
         p->stream = keep;
     };
+    if (p->time_kind == KS_TIME_FWD_LEVEL0 && p->l0 >= 2) {
+        // the bracketed level-0 launch stays eager (events captured inside a
+        // graph would lengthen it); the rest of the pass replays as a graph
+        enqueue_forward(p, H, F, c, K, G, o, C, 1);
+        auto rest = [&](hipStream_t st) {
+            hipStream_t keep = p->stream;
+            p->stream = st;
+            enqueue_forward(p, H, F, c, K, G, o, C, 2);
+            enqueue_backward(p, u_out, cov_out, lag1_out);
+            p->stream = keep;
+        };
+        const void *key[11] = {H, F, c, K, G, o, C, u_out, cov_out, lag1_out, &p->l0};
+        p->graph.run(p->stream, key, 11, rest);
+        return;
+    }
     if (p->time_kind != KS_TIME_OFF) {
         enqueue(p->stream);
         return;

@@ -78,3 +78,27 @@ def test_plan_graph_replays_report_errors_per_call(monkeypatch):
                 plan.smooth_cov(*args, u_out=u, cov_out=S)
     finally:
         plan.close()
+
+
+def test_timed_level0_calls_replay_the_rest(monkeypatch):
+    """A call timing the level-0 launch runs level 0 eagerly between its events
+    and replays the rest of the pass; every call is bitwise the eager pass and
+    adds one bracketed launch to the timer."""
+    monkeypatch.delenv("KS_NO_GRAPH", raising=False)
+    p = gen.workload(1, k=20000)
+    args = ks.to_device(p)
+    plan = ks.Plan(p.k, p.n, p.m, p.K_diag, p.C_diag)
+    u = torch.empty((p.k + 1, p.n), dtype=torch.float64, device="cuda")
+    S = torch.empty((p.k + 1, p.n, p.n), dtype=torch.float64, device="cuda")
+    try:
+        ref = _eager(p, args, monkeypatch, lambda pl, a: pl.smooth_cov(*a))
+        plan.time_kernels(ks.KS_TIME_FWD_LEVEL0)
+        for call in range(4):
+            plan.smooth_cov(*args, u_out=u, cov_out=S)
+            torch.cuda.synchronize()
+            assert np.array_equal(u.cpu().numpy(), ref[0]) and np.array_equal(S.cpu().numpy(), ref[1]), call
+            ms, cnt = plan.kernel_time()
+            assert cnt == call + 1 and ms > 0.0
+        plan.time_kernels(ks.KS_TIME_OFF)
+    finally:
+        plan.close()
