@@ -125,7 +125,23 @@ def cpu_baseline(p, budget_s: float = 10.0):
             break
     return dict(value=(p.k + 1) * reps / el, unit="steps/s", cores=1, kind="oracle",
                 sample=f"the full workload (k={p.k}, n={p.n}, m={p.m}) solved {reps} times "
-                       f"in {el:.1f} s, one thread, C FP64")
+                       f"in {el:.1f} s, one thread, C FP64",
+                host=host_cpu())
+
+
+def host_cpu() -> str:
+    """CPU model name and logical CPU count of this host."""
+    model = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{model}, {os.cpu_count()} logical CPUs"
+
 
 
 def main():
