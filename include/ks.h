@@ -157,6 +157,33 @@ ks_status ks_objective(ks_plan *plan, const double *H, const double *F,
                        const double *o, const double *C, const double *u,
                        double *terms_out, double *total);
 
+/* ------------------------------------------------ allocation-free variant
+ *
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc) and cannot
+ * hand in a workspace either: ks_smooth_cov_static computes what ks_create +
+ * ks_smooth_cov + ks_destroy would (same kernels, same schedule, bitwise the
+ * same states and covariances), but keeps the plan's working data (R rows,
+ * reduced systems, stored S blocks, status word) in a static device array of
+ * KS_STATIC_SCRATCH_BYTES that the library holds on each GPU it runs on until
+ * the process ends.  It creates no plan, stream, event or graph and calls no
+ * device allocation routine.  desc, the inputs and the outputs are as for
+ * ks_create / ks_smooth_cov (device pointers; H may be NULL); hip_stream is
+ * the caller's stream (NULL = default stream), and the call synchronizes on
+ * it before returning.  Errors: KS_E_ARG for an invalid or unsupported
+ * description or a NULL required pointer; KS_E_WORKSPACE when
+ * ks_workspace_bytes(desc) exceeds KS_STATIC_SCRATCH_BYTES (nothing is
+ * launched); KS_E_HIP when the array's device address cannot be obtained;
+ * otherwise the statuses of ks_smooth_cov.  Every call on one GPU uses that
+ * GPU's array: calls that overlap on one GPU (other threads, other streams)
+ * race and must be serialized by the caller. */
+#define KS_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+
+ks_status ks_smooth_cov_static(const ks_desc *desc, const double *H, const double *F,
+                               const double *c, const double *K, const double *G,
+                               const double *o, const double *C, double *u_out,
+                               double *cov_out, void *hip_stream);
+
 /* Release the plan's host state (the workspace stays the caller's). */
 ks_status ks_destroy(ks_plan *plan);
 

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "ks.h"
+
 namespace ks {
 
 // status bits written by kernels into the workspace's flag word
@@ -128,6 +130,15 @@ struct KernelSetList {
 
 // nullptr when (n, m) has no instantiation
 const KernelSet *find_kernels(int n, int m);
+
+// One states + covariances pass (ks_smooth_cov's kernels and schedule) on a
+// workspace the caller provides, without a plan object kept or any stream,
+// event or graph created; synchronizes on the stream.  Validates everything
+// ks_create and ks_smooth_cov validate.
+ks_status smooth_cov_on(const ks_desc *desc, void *workspace, size_t ws_bytes, hipStream_t stream,
+                        const double *H, const double *F, const double *c, const double *K,
+                        const double *G, const double *o, const double *C, double *u_out,
+                        double *cov_out);
 
 void launch_clear_flags(unsigned *flags, hipStream_t s);
 void launch_clear_flags_n(unsigned *flags, int32_t count, hipStream_t s);

@@ -725,6 +725,44 @@ ks_status ks_kernel_time(const ks_plan *p, double *total_ms, int64_t *count) {
 
 }  // extern "C"
 
+namespace ks {
+
+ks_status smooth_cov_on(const ks_desc *desc, void *workspace, size_t ws_bytes, hipStream_t stream,
+                        const double *H, const double *F, const double *c, const double *K,
+                        const double *G, const double *o, const double *C, double *u_out,
+                        double *cov_out) {
+    if (!valid_desc(desc) || !u_out || !cov_out) return KS_E_ARG;
+    const KernelSet *kset = find_kernels(desc->n, desc->m);
+    if (!kset) return KS_E_ARG;
+    ks_plan p;  // host state on the stack: no graph, no timing events
+    if (!make_layout(desc, kset, &p.lo)) return KS_E_ARG;
+    if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0 || ws_bytes < p.lo.total)
+        return KS_E_WORKSPACE;
+    p.d = *desc;
+    p.stream = stream;
+    p.ws = static_cast<char *>(workspace);
+    p.kset = kset;
+    p.smoothed = false;
+    p.host_flags = 0;
+    p.time_kind = KS_TIME_OFF;
+    p.time_armed = false;
+    p.ev_made = false;
+    p.time_ms = 0.0;
+    p.time_count = 0;
+    for (int mode = 0; mode < 3; ++mode) {  // as ks_create
+        const Schedule sc = make_schedule(*desc, kset, p.lo, mode);
+        p.l_switch = sc.l_switch;
+        p.l0 = sc.l0;
+        p.l1[mode] = sc.l1;
+        p.rank_tol = sc.rank_tol;
+    }
+    if (!inputs_ok(&p, F, c, K, G, o, C)) return KS_E_ARG;
+    run_pass(&p, H, F, c, K, G, o, C, u_out, cov_out, nullptr);
+    return finish(&p);
+}
+
+}  // namespace ks
+
 // ====================================================================== batch
 //
 // Many problems (any mix of n, m, k, covariance layouts and precision forms)

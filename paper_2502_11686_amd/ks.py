@@ -28,7 +28,8 @@ SYMBOLS = ("ks_workspace_bytes", "ks_supported", "ks_create", "ks_smooth", "ks_c
            "ks_time_kernels", "ks_kernel_time", "ks_batch_workspace_bytes", "ks_batch_create",
            "ks_batch_smooth", "ks_batch_destroy", "ks_engine_create", "ks_engine_submit",
            "ks_engine_step", "ks_engine_retired", "ks_engine_poll", "ks_engine_query", "ks_engine_destroy",
-           "ks_set_tuning", "ks_get_tuning", "ks_plan_schedule", "ks_smooth_cov_lag1", "ks_objective")
+           "ks_set_tuning", "ks_get_tuning", "ks_plan_schedule", "ks_smooth_cov_lag1", "ks_objective",
+           "ks_smooth_cov_static")
 KS_TIME_OFF, KS_TIME_FWD_LEVEL0, KS_TIME_BWD_LEVEL0, KS_TIME_FWD_ALL, KS_TIME_BWD_ALL = range(5)
 
 
@@ -133,6 +134,8 @@ def lib():
     L.ks_plan_schedule.restype = ctypes.c_int
     L.ks_plan_schedule.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                    ctypes.POINTER(ctypes.c_int32)]
+    L.ks_smooth_cov_static.restype = ctypes.c_int
+    L.ks_smooth_cov_static.argtypes = [ctypes.POINTER(Desc)] + [dp] * 9 + [vp]
     _lib = L
     if not os.environ.get("KS_NO_TUNE"):
         path = os.environ.get("KS_TUNE_FILE", TUNE_PATH)
@@ -388,6 +391,28 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+STATIC_SCRATCH_BYTES = 64 << 20  # KS_STATIC_SCRATCH_BYTES of include/ks.h
+
+
+def smooth_cov_static(shape, inputs, u_out=None, cov_out=None, device=None, stream=None):
+    """States and covariances through ks_smooth_cov_static (the library's
+    static device array as working memory; nothing allocated on the device
+    beyond the outputs when they are not given).  shape = (k, n, m, K_diag,
+    C_diag, fp32); inputs = (H, F, c, K, G, o, C) device tensors."""
+    k, n = int(shape[0]), int(shape[1])
+    dev = _device(device)
+    st_obj = stream if stream is not None else torch.cuda.current_stream(dev)
+    u = u_out if u_out is not None else torch.empty((k + 1, n), dtype=torch.float64, device=dev)
+    cov = cov_out if cov_out is not None else torch.empty((k + 1, n, n), dtype=torch.float64, device=dev)
+    io = _make_io(shape, inputs, u, cov, dev)
+    d = make_desc(*shape)
+    st = lib().ks_smooth_cov_static(ctypes.byref(d), io.H, io.F, io.c, io.K, io.G, io.o, io.C, io.u_out,
+                                    io.cov_out, ctypes.c_void_p(st_obj.cuda_stream))
+    if st != KS_OK:
+        raise KsError(st, "ks_smooth_cov_static")
+    return u, cov
 
 
 def to_device(p, device="cuda"):

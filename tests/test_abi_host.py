@@ -189,3 +189,21 @@ def test_tuning_table_drives_the_schedule(monkeypatch):
         monkeypatch.delenv("KS_TAIL_PASSES", raising=False)
         for fp32, e in zip((False, True), saved):
             ks.set_tuning(5, fp32, e["fwd_tail_passes"], e["bwd_tail_passes"], e["fp32_switch_columns"])
+
+
+def test_static_entry_rejects_oversized_and_invalid_problems():
+    """ks_smooth_cov_static refuses, before any HIP call, a problem whose
+    working data exceed its static array (KS_E_WORKSPACE) and an invalid
+    description or missing output (KS_E_ARG); the pointers are never used."""
+    L = ks.lib()
+    fake = ctypes.c_void_p(1 << 20)
+    k = 200000  # n = 6: about 0.5 GB of working data
+    assert ks.workspace_bytes(k, 6, 3, False, False) > ks.STATIC_SCRATCH_BYTES
+    d = ks.make_desc(k, 6, 3, False, False)
+    assert L.ks_smooth_cov_static(ctypes.byref(d), *([fake] * 9), None) == ks.KS_E_WORKSPACE
+    small = ks.make_desc(1000, 6, 3, False, False)
+    assert ks.workspace_bytes(1000, 6, 3, False, False) <= ks.STATIC_SCRATCH_BYTES
+    assert L.ks_smooth_cov_static(ctypes.byref(small), *([fake] * 7), None, fake, None) == ks.KS_E_ARG
+    bad = ks.make_desc(1000, 7, 3, False, False)  # no kernels for n = 7
+    assert L.ks_smooth_cov_static(ctypes.byref(bad), *([fake] * 9), None) == ks.KS_E_ARG
+    assert L.ks_smooth_cov_static(None, *([fake] * 9), None) == ks.KS_E_ARG
