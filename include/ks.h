@@ -227,22 +227,43 @@ ks_status ks_kernel_time(const ks_plan *plan, double *total_ms, int64_t *count);
 /* ---------------------------------------------------------------- tuning
  *
  * The schedule's free choices, per state dimension n (1..64) and precision
- * form: the top levels that need at most fwd_tail_passes (bwd_tail_passes)
- * passes of the single-workgroup forward (backward) tail kernel run inside
- * it instead of one launch each (0: the base level only), and in the FP32
- * form the levels with more than fp32_switch_columns block columns run in
- * FP32.  None of them changes what is computed beyond rounding order: the
- * tail and per-level kernels do the same arithmetic, so FP64 results are
- * bitwise independent of the pass counts.  Defaults 2, 2, 1024; an autotuned
- * table is applied by the Python binding; the environment variables
- * KS_TAIL_PASSES (both pass counts) and KS_FP32_SWITCH override every entry.
- * Plans, batches and engine requests read the table when they are created;
- * not safe to call concurrently with those. */
-ks_status ks_set_tuning(int32_t n, int32_t precision, int32_t fwd_tail_passes, int32_t bwd_tail_passes,
-                        int64_t fp32_switch_columns);
+ * form.  None of them changes what is computed: every unit and block row
+ * does the same arithmetic whichever launch runs it, so FP64 results are
+ * bitwise independent of them (the FP32 switch changes which levels run in
+ * FP32, hence FP32-form results).
+ *   fwd_tail_passes, bwd_tail_passes: the top levels that need at most that
+ *     many passes of the single-workgroup forward (backward) tail kernel run
+ *     inside it instead of one launch each (0: the base level only);
+ *   fp32_switch_columns: in the FP32 form, the levels with more block columns
+ *     than this run in FP32;
+ *   fwd_group, fwd_group_from: from level fwd_group_from on, fwd_group
+ *     consecutive forward levels run in one launch whose workgroups each own
+ *     an aligned subtree of units (units read only what their own workgroup
+ *     wrote one level down, so levels are separated by workgroup barriers);
+ *     1 = one launch per level;
+ *   bwd_group, bwd_group_from: the same for the backward levels below the
+ *     backward tail (groups bwd_group_from + q bwd_group .. + bwd_group - 1).
+ * Groups apply to single plans (ks_smooth*, ks_covariances,
+ * ks_smooth_cov_static) where the kernel family has group kernels, never
+ * cross the FP32 switch and stay below the tails.  Defaults 2, 2, 1024,
+ * 1, 1, 1, 1; an autotuned table is applied by the Python binding; the
+ * environment variables KS_TAIL_PASSES (both pass counts), KS_FP32_SWITCH,
+ * KS_FWD_GROUP, KS_FWD_GROUP_FROM, KS_BWD_GROUP and KS_BWD_GROUP_FROM
+ * override every entry.  Plans, batches and engine requests read the table
+ * when they are created; not safe to call concurrently with those. */
+typedef struct {
+    int32_t fwd_tail_passes;
+    int32_t bwd_tail_passes;
+    int64_t fp32_switch_columns;   /* >= 1 */
+    int32_t fwd_group;             /* 1..8 */
+    int32_t fwd_group_from;        /* >= 0 */
+    int32_t bwd_group;             /* 1..8 */
+    int32_t bwd_group_from;        /* >= 0 */
+} ks_tuning;
+
+ks_status ks_set_tuning(int32_t n, int32_t precision, const ks_tuning *t);
 /* effective values (environment overrides applied) */
-ks_status ks_get_tuning(int32_t n, int32_t precision, int32_t *fwd_tail_passes, int32_t *bwd_tail_passes,
-                        int64_t *fp32_switch_columns);
+ks_status ks_get_tuning(int32_t n, int32_t precision, ks_tuning *out);
 /* the plan's schedule: number of FP32 levels, first level of the forward tail
  * launch, lowest level of the backward tail launch (states + covariances) */
 ks_status ks_plan_schedule(const ks_plan *plan, int32_t *fp32_levels, int32_t *fwd_tail_level,
@@ -290,63 +311,88 @@ ks_status ks_batch_destroy(ks_batch *batch);
  * Continuous batching for a stream of requests (one smoothing problem each,
  * Section III's forward elimination, the back-substitution, and optionally
  * Algorithm 2's covariances).  The engine owns a caller-given device
- * workspace: 1/16 of it (at least 256 KiB) holds per-tick launch tables and
- * 4096 status words, the rest is handed out as one region per admitted
- * request, of exactly ks_workspace_bytes(desc) rounded up to 256 bytes (first
- * fit over a free list that merges neighbours on release).  Each
- * ks_engine_step advances every in-flight request by one step of its schedule
- * -- one forward level (with its fold), the forward tail, the backward tail or
- * one backward level -- with one launch per kernel class, step kind and
- * precision variant covering all requests at that step, so a request admitted
- * between ticks starts its level 0 in the same launches that carry older
- * requests through their top levels.  A request's schedule is that of a
- * single plan: its results are bitwise those of ks_smooth_cov (want_cov != 0)
- * or ks_smooth on it alone.  Host-side state is not thread-safe: one thread
- * drives an engine. */
+ * workspace: 1/16 of it (at least 256 KiB) holds two buffers of per-tick
+ * launch tables and 4096 status words, the rest is handed out as one region
+ * per admitted request, of exactly ks_workspace_bytes(desc) rounded up to 256
+ * bytes (first fit over a free list that merges neighbours on release).  Each
+ * tick advances every request that still has steps to launch by one step of
+ * its schedule -- one forward level (with its fold), the forward tail, the
+ * backward tail or one backward level -- with one launch per kernel class,
+ * step kind and precision variant covering all requests at that step, so a
+ * request admitted between ticks starts its level 0 in the same launches that
+ * carry older requests through their top levels.  A request's schedule is
+ * that of a single plan: its results are bitwise those of ks_smooth_cov
+ * (want_cov != 0) or ks_smooth on it alone.
+ *
+ * Engine calls are asynchronous: ks_engine_step enqueues a tick on the
+ * engine's stream and returns; at most two ticks are in flight (their launch
+ * tables alternate between the two buffers), so a step that finds both in
+ * flight first waits for the older one.  Requests may be submitted while ticks
+ * run.  A request is finished once the tick holding its last step has
+ * completed; ks_engine_step, ks_engine_retired and ks_engine_poll notice
+ * completed ticks without blocking, ks_engine_wait blocks until every
+ * enqueued tick has completed.  Only then are a finished request's outputs
+ * final and its region and status word free.  Host-side state is not
+ * thread-safe: one thread drives an engine.
+ *
+ * Deliberate differences from a flat "inputs[7]" interface: a request's
+ * device pointers come in the batch API's ks_io struct, covariances
+ * are asked for by want_cov (ks_desc.flags stays reserved; H = NULL means
+ * H_i = I), and tuning is the process-wide table of ks_set_tuning rather than
+ * a per-engine JSON string. */
 typedef struct ks_engine ks_engine;
 
 typedef struct {
-    int64_t inflight;         /* admitted, not finished                        */
-    int64_t retired_pending;  /* finished, not yet collected by ks_engine_retired */
-    int64_t ticks;            /* ks_engine_step calls that launched work       */
-    size_t region_bytes;      /* workspace bytes for request regions           */
-    size_t free_bytes;        /* of which free                                 */
+    int64_t inflight;         /* admitted, not yet retired                       */
+    int64_t retired_pending;  /* retired, not yet collected by ks_engine_retired  */
+    int64_t ticks;            /* ticks enqueued                                   */
+    size_t region_bytes;      /* workspace bytes for request regions             */
+    size_t free_bytes;        /* of which free                                   */
     size_t largest_free;      /* largest free extent (bounds the next admission) */
+    int64_t ticks_pending;    /* enqueued ticks not yet seen complete (0..2)     */
 } ks_engine_stats;
 
 /* workspace: device memory, 256-byte aligned, at least 1 MiB, caller-owned
- * and kept alive until ks_engine_destroy; all work goes to hip_stream. */
+ * and kept alive until ks_engine_destroy; all work goes to hip_stream.
+ * Host-only: the first step creates two events and 32 KiB of pinned host
+ * memory (KS_E_HIP from that step if it fails). */
 ks_status ks_engine_create(void *workspace, size_t ws_bytes, void *hip_stream, ks_engine **out);
 
-/* Admit one request; host-only (launches nothing).  io points to device
- * arrays laid out as for ks_smooth_cov, which must stay valid and unchanged
- * (outputs: untouched by the caller) until the request is retired.
- * KS_E_BUSY: no free region, table share or status word right now -- retry
- * after a step; KS_E_WORKSPACE: the request can never fit this engine;
- * KS_E_ARG: bad description or pointer.  *ticket identifies the request. */
+/* Admit one request; host-only (launches nothing), also while ticks run.  io
+ * points to device arrays laid out as for ks_smooth_cov, which must stay
+ * valid and unchanged (outputs: untouched by the caller) until the request is
+ * retired.  KS_E_BUSY: no free region, table share or status word right now
+ * -- retry after a step; KS_E_WORKSPACE: the request can never fit this
+ * engine; KS_E_ARG: bad description or pointer.  *ticket identifies the
+ * request. */
 ks_status ks_engine_submit(ks_engine *engine, const ks_desc *desc, const ks_io *io, int32_t want_cov,
                            uint64_t *ticket);
 
-/* One tick (synchronous: returns after the tick's kernels have finished).
- * *finished (may be NULL) receives the number of requests that completed;
- * their regions are free again and their outputs are final. */
+/* Retire the requests of completed ticks, then enqueue one tick (nothing when
+ * no request has steps left to launch) and return without waiting for it.
+ * *finished (may be NULL) receives the number of requests retired by this
+ * call. */
 ks_status ks_engine_step(ks_engine *engine, int32_t *finished);
 
-/* Collect up to capacity finished requests, oldest first: ticket and status
+/* Block until every enqueued tick has completed and retire their requests;
+ * *finished (may be NULL) as for ks_engine_step. */
+ks_status ks_engine_wait(ks_engine *engine, int32_t *finished);
+
+/* Collect up to capacity retired requests, oldest first: ticket and status
  * (KS_OK, KS_E_NOT_SPD, KS_E_NONFINITE or KS_E_RANK, as ks_smooth_cov would
  * return).  *count receives how many were written. */
 ks_status ks_engine_retired(ks_engine *engine, int32_t capacity, uint64_t *tickets,
                             ks_status *statuses, int32_t *count);
 
-/* The status of one request: KS_OK with *result set once it has finished
- * (it is then removed from the retired list), KS_E_BUSY while it is in
- * flight, KS_E_ARG for a ticket that is neither (unknown or collected). */
+/* The status of one request: KS_OK with *result set once it is retired (it
+ * is then removed from the retired list), KS_E_BUSY while it is not, KS_E_ARG
+ * for a ticket that is neither (unknown or collected). */
 ks_status ks_engine_poll(ks_engine *engine, uint64_t ticket, ks_status *result);
 
 ks_status ks_engine_query(const ks_engine *engine, ks_engine_stats *out);
 
-/* Frees host state only; requests still in flight are abandoned (no kernels
- * are outstanding between steps). */
+/* Waits for the engine's stream, then frees host state; requests not yet
+ * retired are abandoned. */
 ks_status ks_engine_destroy(ks_engine *engine);
 
 #ifdef __cplusplus

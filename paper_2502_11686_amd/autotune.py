@@ -75,21 +75,21 @@ def tune_one(n: int, fp32: bool, reps: int = 7) -> dict:
     sw = base["fp32_switch_columns"]
     fwd = {}
     for q in PASSES:
-        ks.set_tuning(n, fp32, q, base["bwd_tail_passes"], sw)
+        ks.set_tuning(n, fp32, fwd_tail_passes=q, bwd_tail_passes=base["bwd_tail_passes"], fp32_switch_columns=sw)
         fwd[q] = _timed(p, args, fp32, ks.KS_TIME_FWD_ALL, reps)
     best_f = min(fwd, key=fwd.get)
     bwd = {}
     for q in PASSES:
-        ks.set_tuning(n, fp32, best_f, q, sw)
+        ks.set_tuning(n, fp32, fwd_tail_passes=best_f, bwd_tail_passes=q, fp32_switch_columns=sw)
         bwd[q] = _timed(p, args, fp32, ks.KS_TIME_BWD_ALL, reps)
     best_b = min(bwd, key=bwd.get)
     best_s, sws = sw, {}
     if fp32:
         for s in SWITCHES:
-            ks.set_tuning(n, fp32, best_f, best_b, s)
+            ks.set_tuning(n, fp32, fwd_tail_passes=best_f, bwd_tail_passes=best_b, fp32_switch_columns=s)
             sws[s] = _timed(p, args, fp32, None, reps)
         best_s = min(sws, key=sws.get)
-    ks.set_tuning(n, fp32, best_f, best_b, best_s)
+    ks.set_tuning(n, fp32, fwd_tail_passes=best_f, bwd_tail_passes=best_b, fp32_switch_columns=best_s)
     return dict(n=n, form="fp32" if fp32 else "fp64", fwd_tail_passes=best_f, bwd_tail_passes=best_b,
                 fp32_switch_columns=best_s, k=p.k,
                 fwd_ms={str(q): round(v, 4) for q, v in fwd.items()},

@@ -460,12 +460,13 @@ __device__ __forceinline__ void fold_part(const FwdArgs &a, int64_t t, int gl, i
 // per-level kernels leave that to k_fold).  No workgroup barrier.
 template <int N, int MM, bool RAW, bool INLINE_FOLD, class T, class TIN>
 __device__ __forceinline__ void fwd_unit(const FwdArgs &a, int64_t t, bool in, int gl, int gb,
-                                         double &dmin, double &dmax, bool &bad, bool &nonfinite) {
+                                         double &dmin, double &dmax, bool &bad, bool &nonfinite,
+                                         int64_t t_end = -1) {
     using GE = Geo<N>;
     constexpr int RO = RAW ? MM : N;            // rows of an observation block
     constexpr int HA = RO + N, HB = 2 * RO, HC = 2 * N;
     constexpr int PB = HB < N ? HB : N;         // rows of the step-3 triangle
-    const bool valid = in && t < a.units;
+    const bool valid = in && t < (t_end < 0 ? a.units : t_end);
     const LaneRole<N> L(gl);
     const int64_t j = 2 * t;
     const bool fold = valid && (a.Nl & 1) && t == a.units - 1;
@@ -642,7 +643,8 @@ __global__ __launch_bounds__(kBlock) void k_fold(FwdArgs a0, const FwdArgs *tab,
 
 // Levels l0..L in one workgroup (the small levels at the top of the
 // recursion): each level is a loop of unit passes, levels are separated by a
-// device-scope fence and a workgroup barrier.  Ends with the rank test over
+// workgroup barrier (a level reads only what this workgroup wrote one level
+// down, or what earlier launches wrote).  Ends with the rank test over
 // the per-block slots of the earlier launches and its own diagonal.
 template <int N, int MM, bool RAW0, bool BATCH>
 __global__ __launch_bounds__(kTailBlock) void k_fwd_tail(FwdTailArgs ta0, const FwdTailArgs *tab,
@@ -674,12 +676,63 @@ __global__ __launch_bounds__(kTailBlock) void k_fwd_tail(FwdTailArgs ta0, const 
                     fwd_unit<N, MM, false, true, double, double>(a, t0 + g.ui, g.in, g.gl, g.gbase, dmin, dmax, bad, nonfinite);
             }
         }
-        __threadfence();
-        __syncthreads();
+        __syncthreads();  // the next level reads what this workgroup wrote: workgroup scope suffices
     }
     reduce_slots(ta.slots, ta.nprev, dmin, dmax);
     block_minmax<kTailBlock>(dmin, dmax, bad, nonfinite, ta.a.flags);
     rank_flag(dmin, dmax, ta.rank_tol, ta.a.flags);
+}
+
+// A group of consecutive forward levels l_first .. l_first + nlev - 1 in one
+// launch (subtree fusion).  Workgroup w owns the level-l_first units
+// [w U, (w+1) U) -- the last workgroup also the rest of the level -- and, at
+// level l_first + x, the units [w U / 2^x, (w+1) U / 2^x) (the last one again
+// to the level's end).  Those units read exactly the reduced columns the
+// workgroup wrote one level down (unit t of level l writes reduced column t of
+// level l+1 and reads columns 2t, 2t+1 and, for the fold, the level's last
+// column), so levels are separated by workgroup barriers only.  U is a
+// multiple of 2^(nlev-1).  The arithmetic of every unit is that of the
+// per-level kernels.  One [min, max] slot per workgroup.
+template <int N, int MM, bool RAW0, class T, class TIN>
+__global__ __launch_bounds__(kBlock) void k_fwd_multi(FwdMultiArgs ma) {
+    using GE = Geo<N>;
+    const Grp<N> g;
+    bool bad = false, nonfinite = false;
+    double dmin = INFINITY, dmax = 0.0;
+    const int64_t w = blockIdx.x;
+    for (int x = 0; x < ma.nlev; ++x) {
+        const int l = ma.l_first + x;
+        FwdArgs a = ma.a;
+        a.Nl = ma.Nl[l];
+        a.units = a.Nl / 2;
+        a.level = l;
+        a.sys_in = l >= 1 ? ma.sys + ma.sys_off[l] : nullptr;
+        a.sys_out = ma.sys + ma.sys_off[l + 1];
+        a.rrows = ma.rrows + ma.rec_off[l] * GE::RREC;
+        const int64_t span = ma.U >> x;
+        const int64_t lo = w * span;
+        const int64_t hi = (w == ma.groups - 1) ? a.units : lo + span;
+        for (int64_t t0 = lo; t0 < hi; t0 += GE::UPB) {
+            if (x == 0) {
+                fwd_unit<N, MM, RAW0, true, T, TIN>(a, t0 + g.ui, g.in, g.gl, g.gbase, dmin, dmax, bad,
+                                                    nonfinite, hi);
+            } else {
+                fwd_unit<N, MM, false, true, T, T>(a, t0 + g.ui, g.in, g.gl, g.gbase, dmin, dmax, bad,
+                                                   nonfinite, hi);
+            }
+        }
+        if (x + 1 < ma.nlev) __syncthreads();  // the next level reads what this one wrote
+    }
+    block_minmax<kBlock>(dmin, dmax, bad, nonfinite, ma.a.flags);
+    if (threadIdx.x == 0) {
+        ma.slots[2 * w] = dmin;
+        ma.slots[2 * w + 1] = dmax;
+    }
+    // the rest of the group's slot region (read by the rank test) is neutral
+    for (int64_t q = ma.groups + w * kBlock + threadIdx.x; q < ma.slot_pairs; q += ma.groups * kBlock) {
+        ma.slots[2 * q] = INFINITY;
+        ma.slots[2 * q + 1] = 0.0;
+    }
 }
 
 // ------------------------------------------------------------ backward level
@@ -896,8 +949,7 @@ __global__ __launch_bounds__(TB) void k_bwd_tail(BwdArgs a0, const BwdArgs *tab,
         for (int64_t t0 = 0; t0 < units; t0 += UPB)
             bwd_unit<N, DO_Y, DO_COV, double>(a, l, t0 + g.ui, units, a.store_s && l >= 1, g.in, g.gl,
                                       smem + g.ui * SM::PER);
-        __threadfence();
-        __syncthreads();
+        __syncthreads();  // the next level reads what this workgroup wrote: workgroup scope suffices
     }
 }
 
@@ -922,6 +974,11 @@ static void launch_fwd_fold_t(const FwdArgs &a, hipStream_t s) {
     const int64_t blocks = (a.units + Geo<N>::UPB - 1) / Geo<N>::UPB;
     hipLaunchKernelGGL((k_forward<N, MM, false, T, TIN, false, true>), dim3((unsigned)blocks), dim3(kBlock), 0,
                        s, a, nullptr, BlockMap{});
+}
+
+template <int N, int MM, bool RAW0, class T, class TIN>
+static void launch_fwd_multi_t(const FwdMultiArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL((k_fwd_multi<N, MM, RAW0, T, TIN>), dim3((unsigned)a.groups), dim3(kBlock), 0, s, a);
 }
 
 template <int N, int MM, bool RAW, class T, class TIN>
@@ -985,7 +1042,7 @@ static void launch_bwd_tail_bt(const BwdArgs *tab, BlockMap bm, int64_t blocks, 
 // variants: forward [FP64 | FP32 | FP64 from FP32 records (switch level)],
 // backward [mode][record type FP64 | FP32]
 template <int N, int MM>
-constexpr KernelSet make_set() {
+constexpr KernelSet make_set_base() {
     return KernelSet{N,
                      MM,
                      {&launch_fwd_t<N, MM, true, double, double>, &launch_fwd_t<N, MM, true, float, double>},
@@ -1022,6 +1079,18 @@ constexpr KernelSet make_set() {
                       (BwdTailBlock<N, true, true>::TB / 64) * Geo<N>::UPW},
                      {&launch_fwd_fold_t<N, MM, double, double>, &launch_fwd_fold_t<N, MM, float, float>,
                       &launch_fwd_fold_t<N, MM, double, float>}};
+}
+
+template <int N, int MM>
+constexpr KernelSet make_set() {
+    KernelSet s = make_set_base<N, MM>();
+    s.fwd_multi_raw[0] = &launch_fwd_multi_t<N, MM, true, double, double>;
+    s.fwd_multi_raw[1] = &launch_fwd_multi_t<N, MM, true, float, double>;
+    s.fwd_multi[FV_F64] = &launch_fwd_multi_t<N, MM, false, double, double>;
+    s.fwd_multi[FV_F32] = &launch_fwd_multi_t<N, MM, false, float, float>;
+    s.fwd_multi[FV_F64_FROM_F32] = &launch_fwd_multi_t<N, MM, false, double, float>;
+    s.upb_multi = Geo<N>::UPB;
+    return s;
 }
 
 #define KS_SETS(N) make_set<N, (N + 1) / 2>(), make_set<N, N>(), make_set<N, 2 * N>()

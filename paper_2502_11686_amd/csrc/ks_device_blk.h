@@ -328,8 +328,31 @@ __global__ __launch_bounds__(BGeo<N>::TBB) void k_blk_bwd_tail(BwdArgs a0, const
         const int64_t units = (a.Nl[l] + 1) / 2;
         for (int64_t t0 = 0; t0 < units; t0 += BG::RPW)
             blk_bwd_unit<N, DO_Y, DO_COV, double>(a, l, t0 + u, units, a.store_s && l >= 1, sm + u * PER);
-        __threadfence();
-        __syncthreads();
+        __syncthreads();  // the next level reads what this workgroup wrote: workgroup scope suffices
+    }
+}
+
+// Backward levels a.level down to a.l_lo in one launch (subtree fusion):
+// workgroup c owns the records whose columns i satisfy
+// c 2^(level+1) < i + 1 < (c+1) 2^(level+1), i.e. records
+// [c 2^(level-l), (c+1) 2^(level-l)) of level l.  Every neighbour such a record
+// reads (i +- 2^l, and the S block one of them stored) lies inside that range,
+// where this workgroup wrote it one level up, or on its ends, which earlier
+// launches wrote; so levels are separated by workgroup barriers only.
+template <int N, bool DO_Y, bool DO_COV, class TR>
+__global__ __launch_bounds__(BGeo<N>::TBB) void k_blk_bwd_multi(BwdArgs a) {
+    using BG = BGeo<N>;
+    constexpr int PER = BSmem<N, DO_COV>::PER;
+    __shared__ double sm[BG::RPW * PER];
+    const int u = threadIdx.x / BG::UT;
+    const int64_t c = blockIdx.x;
+    for (int l = a.level; l >= a.l_lo; --l) {
+        const int64_t recs = (a.Nl[l] + 1) / 2;
+        const int64_t span = (int64_t)1 << (a.level - l);
+        const int64_t lo = c * span;
+        const int64_t hi = lo + span < recs ? lo + span : recs;
+        for (int64_t t0 = lo; t0 < hi; t0 += BG::RPW)
+            blk_bwd_unit<N, DO_Y, DO_COV, TR>(a, l, t0 + u, hi, a.store_s && l >= 1, sm + u * PER);
     }
 }
 
@@ -358,8 +381,27 @@ static void launch_blk_bwd_tail_bt(const BwdArgs *tab, BlockMap bm, int64_t bloc
                        BwdArgs{}, tab, bm);
 }
 
+template <int N, bool Y, bool COV, class TR>
+static void launch_blk_bwd_multi_t(const BwdArgs &a, hipStream_t s) {
+    const int64_t recs = (a.Nl[a.l_lo] + 1) / 2;
+    const int64_t span = (int64_t)1 << (a.level - a.l_lo);
+    const int64_t blocks = (recs + span - 1) / span;
+    hipLaunchKernelGGL((k_blk_bwd_multi<N, Y, COV, TR>), dim3((unsigned)blocks), dim3(BGeo<N>::TBB), 0, s, a);
+}
+
+template <int N>
+constexpr void set_blk_bwd_multi(KernelSet &s) {
+    s.bwd_multi[BWD_Y][0] = &launch_blk_bwd_multi_t<N, true, false, double>;
+    s.bwd_multi[BWD_Y][1] = &launch_blk_bwd_multi_t<N, true, false, float>;
+    s.bwd_multi[BWD_COV][0] = &launch_blk_bwd_multi_t<N, false, true, double>;
+    s.bwd_multi[BWD_COV][1] = &launch_blk_bwd_multi_t<N, false, true, float>;
+    s.bwd_multi[BWD_BOTH][0] = &launch_blk_bwd_multi_t<N, true, true, double>;
+    s.bwd_multi[BWD_BOTH][1] = &launch_blk_bwd_multi_t<N, true, true, float>;
+    s.rpp_multi = BGeo<N>::RPW;
+}
+
 template <int N, int MM>
-constexpr KernelSet make_blk_set() {
+constexpr KernelSet make_blk_set_base() {
     return KernelSet{N,
                      MM,
                      {&launch_wg_fwd_t<N, MM, true, double, double>, &launch_wg_fwd_t<N, MM, true, float, double>},
@@ -394,6 +436,13 @@ constexpr KernelSet make_blk_set() {
                      {0, 0, 0},
                      {&launch_wg_fwd_fold_t<N, MM, double, double>, &launch_wg_fwd_fold_t<N, MM, float, float>,
                       &launch_wg_fwd_fold_t<N, MM, double, float>}};
+}
+
+template <int N, int MM>
+constexpr KernelSet make_blk_set() {
+    KernelSet s = make_blk_set_base<N, MM>();
+    set_blk_bwd_multi<N>(s);
+    return s;
 }
 
 #define KS_BLK_SETS(N) make_blk_set<N, wg_mm_small(N)>(), make_blk_set<N, N>()
@@ -431,6 +480,7 @@ constexpr KernelSet make_hyb_set() {
         s.upb_bwd[q] = BGeo<N>::RPW;
         s.upb_bwd_tail[q] = 0;
     }
+    set_blk_bwd_multi<N>(s);
     return s;
 }
 

@@ -700,8 +700,7 @@ __global__ __launch_bounds__(WThreads<N>::NT) void k_wg_fwd_tail(FwdTailArgs ta0
                 __syncthreads();
             }
         }
-        __threadfence();
-        __syncthreads();
+        __syncthreads();  // the next level reads what this workgroup wrote: workgroup scope suffices
     }
     reduce_slots(ta.slots, ta.nprev, dmin, dmax);
     block_minmax<G::NT>(dmin, dmax, bad, nonfinite, ta.a.flags);

@@ -54,7 +54,25 @@ struct FwdTailArgs {
     int64_t Nl[kMaxLevels];
 };
 
-// Arguments of a backward level (back-substitution and/or Algorithm 2); the
+// A group of consecutive forward levels l_first .. l_first + nlev - 1 in one
+// launch (subtree fusion): workgroup w owns the level-l_first units
+// [w U, (w+1) U) (the last workgroup up to the level's end) and every unit
+// they feed at the later levels of the group.  U is a multiple of 2^(nlev-1).
+struct FwdMultiArgs {
+    FwdArgs a;        // shared fields (k, m, layouts, raw inputs, flags)
+    int32_t l_first, nlev;
+    int64_t U;        // level-l_first units per workgroup
+    int64_t groups;   // workgroups
+    double *sys;      // reduced-system segment
+    double *rrows;    // R-row record 0
+    double *slots;    // one [min |R_pp|, max |R_pp|] pair per workgroup, then
+    int64_t slot_pairs;   // ... neutral pairs up to here (the per-level slots the group replaces)
+    int64_t sys_off[kMaxLevels];
+    int64_t rec_off[kMaxLevels];
+    int64_t Nl[kMaxLevels];
+};
+
+// Arguments of a backward level// Arguments of a backward level (back-substitution and/or Algorithm 2); the
 // tail kernel runs levels `level` down to `l_lo`.
 struct BwdArgs {
     int64_t k;
@@ -81,6 +99,7 @@ enum FwdVariant { FV_F64 = 0, FV_F32 = 1, FV_F64_FROM_F32 = 2 };
 using FwdFn = void (*)(const FwdArgs &, hipStream_t);
 using BwdFn = void (*)(const BwdArgs &, hipStream_t);
 using TailFn = void (*)(const FwdTailArgs &, hipStream_t);
+using FwdMFn = void (*)(const FwdMultiArgs &, hipStream_t);
 
 // Batched launches: workgroup b of a launch takes its arguments from table
 // entry item[b]; blk[b] is its block (or record-pass) index within that
@@ -121,6 +140,17 @@ struct KernelSet {
     // levels >= 1 with the odd level's fold done by the level kernel's last
     // unit (no separate fold launch); null where the family has none
     FwdFn fwd_fold[3];
+    // groups of consecutive levels in one launch (subtree fusion), null where
+    // the family has none: forward groups starting at level 0 ([FP64 | FP32])
+    // and above it (indexed by the FwdVariant of the group's first level);
+    // backward groups (BwdArgs: levels `level` down to `l_lo`, workgroup c owns
+    // the records of columns i with c 2^(level+1) < i+1 < (c+1) 2^(level+1)),
+    // [BwdMode][records FP64 | FP32]
+    FwdMFn fwd_multi_raw[2];
+    FwdMFn fwd_multi[3];
+    BwdFn bwd_multi[3][2];
+    int upb_multi;    // units per pass of a forward group workgroup
+    int rpp_multi;    // records per pass of a backward group workgroup
 };
 
 struct KernelSetList {

@@ -230,6 +230,7 @@ struct ks_plan {
     int l0;                // first level of the forward tail launch
     int l1[3];             // lowest level of the backward tail launch, per backward mode
     double rank_tol;
+    int fg, fg_from, bg, bg_from;  // level groups: levels per launch and first grouped level
     // instrumentation (ks_time_kernels)
     int time_kind;
     bool time_armed;       // events of the current call were recorded
@@ -285,6 +286,7 @@ int tail_start(const Layout &lo, int per_pass, int passes, bool backward) {
 struct Tuning {
     int32_t fwd_passes, bwd_passes;
     int64_t switch_cols;
+    int32_t fwd_group, fwd_group_from, bwd_group, bwd_group_from;
 };
 constexpr int kTuneMaxN = 64;
 std::mutex g_tune_mu;
@@ -292,7 +294,7 @@ Tuning g_tune[kTuneMaxN + 1][2];
 bool g_tune_set[kTuneMaxN + 1][2];
 
 Tuning tuning_for(int n, int precision) {
-    Tuning t{2, 2, 1024};
+    Tuning t{2, 2, 1024, 1, 1, 1, 1};
     {
         std::lock_guard<std::mutex> lock(g_tune_mu);
         if (n >= 0 && n <= kTuneMaxN && precision >= 0 && precision < 2 && g_tune_set[n][precision])
@@ -300,6 +302,10 @@ Tuning tuning_for(int n, int precision) {
     }
     if (const char *e = std::getenv("KS_TAIL_PASSES")) t.fwd_passes = t.bwd_passes = std::atoi(e);
     if (const char *e = std::getenv("KS_FP32_SWITCH")) t.switch_cols = std::atoll(e);
+    if (const char *e = std::getenv("KS_FWD_GROUP")) t.fwd_group = std::atoi(e);
+    if (const char *e = std::getenv("KS_FWD_GROUP_FROM")) t.fwd_group_from = std::atoi(e);
+    if (const char *e = std::getenv("KS_BWD_GROUP")) t.bwd_group = std::atoi(e);
+    if (const char *e = std::getenv("KS_BWD_GROUP_FROM")) t.bwd_group_from = std::atoi(e);
     return t;
 }
 
@@ -308,6 +314,7 @@ Tuning tuning_for(int n, int precision) {
 struct Schedule {
     int l_switch, l0, l1;
     double rank_tol;
+    int fg, fg_from, bg, bg_from;  // level groups (single plans)
 };
 
 Schedule make_schedule(const ks_desc &d, const ks::KernelSet *kset, const Layout &lo, int bwd_mode) {
@@ -322,11 +329,35 @@ Schedule make_schedule(const ks_desc &d, const ks::KernelSet *kset, const Layout
     int l1 = tail_start(lo, kset->upb_bwd_tail[bwd_mode], tu.bwd_passes, true);
     sc.l1 = l1 < sc.l_switch ? sc.l_switch : l1;
     sc.rank_tol = 64.0 * (sc.l_switch > 0 ? 1.1920928955078125e-07 : 2.220446049250313e-16);
+    sc.fg = std::max(1, std::min(tu.fwd_group, 8));
+    sc.fg_from = std::max(0, tu.fwd_group_from);
+    sc.bg = std::max(1, std::min(tu.bwd_group, 8));
+    sc.bg_from = std::max(0, tu.bwd_group_from);
     return sc;
 }
 
-// part 0: the whole forward sweep; 1: its head (status clear and level 0);
-// 2: the rest (levels >= 1 and the tail).  Parts 1 and 2 need l0 >= 2.
+// End (exclusive) of the forward launch that starts at level l: a group of
+// fg levels from fg_from on, where the kernel family has group kernels; a
+// group never reaches the tail and never crosses the FP32 switch.
+int fwd_launch_end(const ks_plan *p, int l) {
+    if (p->fg < 2 || l < p->fg_from || !p->kset->fwd_multi[0]) return l + 1;
+    int end = std::min(l + p->fg, p->l0);
+    if (l < p->l_switch) end = std::min(end, p->l_switch);
+    return std::max(end, l + 1);
+}
+
+int64_t lcm64(int64_t a, int64_t b) {
+    int64_t x = a, y = b;
+    while (y) {
+        const int64_t r = x % y;
+        x = y;
+        y = r;
+    }
+    return a / x * b;
+}
+
+// part 0: the whole forward sweep; 1: its head (status clear and the launch
+// holding level 0); 2: the rest (needs a head that ends before the tail).
 void enqueue_forward(ks_plan *p, const double *H, const double *F, const double *c,
                      const double *K, const double *G, const double *o, const double *C, int part = 0) {
     const Layout &lo = p->lo;
@@ -349,8 +380,10 @@ void enqueue_forward(ks_plan *p, const double *H, const double *F, const double 
     a.C_diag = p->d.C_layout == KS_COV_DIAG;
     a.H = H; a.F = F; a.c = c; a.K = K; a.G = G; a.o = o; a.C = C;
     a.flags = flags;
-    const int l_first = part == 2 ? 1 : 0, l_end = part == 1 ? 1 : l0;
-    for (int l = l_first; l < l_end; ++l) {
+    const int head_end = l0 >= 1 ? fwd_launch_end(p, 0) : 0;
+    const int l_first = part == 2 ? head_end : 0, l_end = part == 1 ? head_end : l0;
+    for (int l = l_first; l < l_end;) {
+        const int end = fwd_launch_end(p, l);
         a.Nl = lo.Nl[l];
         a.units = lo.Nl[l] / 2;
         a.level = l;
@@ -362,7 +395,27 @@ void enqueue_forward(ks_plan *p, const double *H, const double *F, const double 
         a.fold_slot = a.slots + 2 * blocks;
         // precision of this level: FP32 below the switch, FP64 from it on
         const int v = l < ls ? ks::FV_F32 : (l == ls && l > 0 ? ks::FV_F64_FROM_F32 : ks::FV_F64);
-        if (l == 0) {
+        if (end - l >= 2) {
+            // levels l .. end-1 in one launch: each workgroup an aligned subtree
+            ks::FwdMultiArgs ma{};
+            ma.a = a;
+            ma.l_first = l;
+            ma.nlev = end - l;
+            ma.U = lcm64(p->kset->upb_multi, (int64_t)1 << (ma.nlev - 1));
+            ma.groups = std::max<int64_t>(1, a.units / ma.U);
+            ma.sys = sys;
+            ma.rrows = rrows;
+            ma.slots = a.slots;
+            ma.slot_pairs = lo.slot_off[end] - lo.slot_off[l];
+            for (int q = 0; q <= lo.L; ++q) {
+                ma.sys_off[q] = lo.sys_off[q];
+                ma.rec_off[q] = lo.rec_off[q];
+                ma.Nl[q] = lo.Nl[q];
+            }
+            if (l == 0) mark(p, KS_TIME_FWD_LEVEL0, 0);
+            (l == 0 ? p->kset->fwd_multi_raw[v == ks::FV_F32] : p->kset->fwd_multi[v])(ma, p->stream);
+            if (l == 0) mark(p, KS_TIME_FWD_LEVEL0, 1);
+        } else if (l == 0) {
             // the level-0 bracket holds the level kernel alone (not the fold)
             mark(p, KS_TIME_FWD_LEVEL0, 0);
             p->kset->fwd_raw[v == ks::FV_F32](a, p->stream);
@@ -374,6 +427,7 @@ void enqueue_forward(ks_plan *p, const double *H, const double *F, const double 
             p->kset->fwd[v](a, p->stream);
             if (lo.Nl[l] & 1) p->kset->fold[v](a, p->stream);
         }
+        l = end;
     }
     if (part == 1) return;
     ks::FwdTailArgs ta{};
@@ -422,12 +476,27 @@ void enqueue_backward(ks_plan *p, double *u_out, double *cov_out, double *lag1_o
         p->kset->bwd_tail[mode](b, p->stream);
         if (l1 == 0) mark(p, KS_TIME_BWD_LEVEL0, 1);
     }
-    for (int l = (l1 <= lo.L ? l1 : lo.L + 1) - 1; l >= 0; --l) {
-        b.level = l;
-        b.l_lo = l;
-        if (l == 0) mark(p, KS_TIME_BWD_LEVEL0, 0);
-        p->kset->bwd[mode][l < p->l_switch ? 1 : 0](b, p->stream);
-        if (l == 0) mark(p, KS_TIME_BWD_LEVEL0, 1);
+    // below the tail: groups of bg levels from bg_from on (highest group
+    // first; a group never crosses the FP32 switch), one launch per level
+    // elsewhere
+    const int top0 = (l1 <= lo.L ? l1 : lo.L + 1) - 1;
+    for (int top = top0; top >= 0;) {
+        int low = top;
+        if (p->bg >= 2 && top >= p->bg_from && p->kset->bwd_multi[mode][0]) {
+            // the group holding `top` in the partition bg_from + q bg of the levels
+            low = p->bg_from + (top - p->bg_from) / p->bg * p->bg;
+            if (top >= p->l_switch && low < p->l_switch) low = p->l_switch;
+        }
+        b.level = top;
+        b.l_lo = low;
+        const int tr = top < p->l_switch ? 1 : 0;
+        if (low == 0) mark(p, KS_TIME_BWD_LEVEL0, 0);
+        if (low < top)
+            p->kset->bwd_multi[mode][tr](b, p->stream);
+        else
+            p->kset->bwd[mode][tr](b, p->stream);
+        if (low == 0) mark(p, KS_TIME_BWD_LEVEL0, 1);
+        top = low - 1;
     }
     mark(p, KS_TIME_BWD_ALL, 1);
 }
@@ -469,7 +538,7 @@ void run_pass(ks_plan *p, const double *H, const double *F, const double *c, con
         enqueue_backward(p, u_out, cov_out, lag1_out);
         p->stream = keep;
     };
-    if (p->time_kind == KS_TIME_FWD_LEVEL0 && p->l0 >= 2) {
+    if (p->time_kind == KS_TIME_FWD_LEVEL0 && p->l0 >= 1 && fwd_launch_end(p, 0) < p->l0) {
         // the bracketed level-0 launch stays eager (events captured inside a
         // graph would lengthen it); the rest of the pass replays as a graph
         enqueue_forward(p, H, F, c, K, G, o, C, 1);
@@ -539,6 +608,10 @@ ks_status ks_create(const ks_desc *desc, void *workspace, size_t ws_bytes, void 
         p->l0 = sc.l0;
         p->l1[mode] = sc.l1;
         p->rank_tol = sc.rank_tol;
+        p->fg = sc.fg;
+        p->fg_from = sc.fg_from;
+        p->bg = sc.bg;
+        p->bg_from = sc.bg_from;
     }
     *out = p;
     return KS_OK;
@@ -654,26 +727,31 @@ const char *ks_status_string(ks_status s) {
     return "unknown status";
 }
 
-ks_status ks_set_tuning(int32_t n, int32_t precision, int32_t fwd_tail_passes, int32_t bwd_tail_passes,
-                        int64_t fp32_switch_columns) {
-    if (n < 1 || n > kTuneMaxN || (precision != KS_FP64 && precision != KS_FP32_FORM) || fwd_tail_passes < 0 ||
-        bwd_tail_passes < 0 || fp32_switch_columns < 1)
+ks_status ks_set_tuning(int32_t n, int32_t precision, const ks_tuning *t) {
+    if (n < 1 || n > kTuneMaxN || (precision != KS_FP64 && precision != KS_FP32_FORM) || !t ||
+        t->fwd_tail_passes < 0 || t->bwd_tail_passes < 0 || t->fp32_switch_columns < 1 || t->fwd_group < 1 ||
+        t->fwd_group > 8 || t->fwd_group_from < 0 || t->bwd_group < 1 || t->bwd_group > 8 ||
+        t->bwd_group_from < 0)
         return KS_E_ARG;
     std::lock_guard<std::mutex> lock(g_tune_mu);
-    g_tune[n][precision] = Tuning{fwd_tail_passes, bwd_tail_passes, fp32_switch_columns};
+    g_tune[n][precision] = Tuning{t->fwd_tail_passes, t->bwd_tail_passes, t->fp32_switch_columns, t->fwd_group,
+                                  t->fwd_group_from, t->bwd_group, t->bwd_group_from};
     g_tune_set[n][precision] = true;
     return KS_OK;
 }
 
-ks_status ks_get_tuning(int32_t n, int32_t precision, int32_t *fwd_tail_passes, int32_t *bwd_tail_passes,
-                        int64_t *fp32_switch_columns) {
-    if (n < 1 || n > kTuneMaxN || (precision != KS_FP64 && precision != KS_FP32_FORM) || !fwd_tail_passes ||
-        !bwd_tail_passes || !fp32_switch_columns)
+ks_status ks_get_tuning(int32_t n, int32_t precision, ks_tuning *out) {
+    if (n < 1 || n > kTuneMaxN || (precision != KS_FP64 && precision != KS_FP32_FORM) || !out)
         return KS_E_ARG;
     const Tuning t = tuning_for(n, precision);
-    *fwd_tail_passes = t.fwd_passes;
-    *bwd_tail_passes = t.bwd_passes;
-    *fp32_switch_columns = t.switch_cols;
+    std::memset(out, 0, sizeof(*out));
+    out->fwd_tail_passes = t.fwd_passes;
+    out->bwd_tail_passes = t.bwd_passes;
+    out->fp32_switch_columns = t.switch_cols;
+    out->fwd_group = t.fwd_group;
+    out->fwd_group_from = t.fwd_group_from;
+    out->bwd_group = t.bwd_group;
+    out->bwd_group_from = t.bwd_group_from;
     return KS_OK;
 }
 
@@ -755,6 +833,10 @@ ks_status smooth_cov_on(const ks_desc *desc, void *workspace, size_t ws_bytes, h
         p.l0 = sc.l0;
         p.l1[mode] = sc.l1;
         p.rank_tol = sc.rank_tol;
+        p.fg = sc.fg;
+        p.fg_from = sc.fg_from;
+        p.bg = sc.bg;
+        p.bg_from = sc.bg_from;
     }
     if (!inputs_ok(&p, F, c, K, G, o, C)) return KS_E_ARG;
     run_pass(&p, H, F, c, K, G, o, C, u_out, cov_out, nullptr);
@@ -1258,22 +1340,34 @@ struct EngReq {
 
 constexpr int32_t kEngSlots = 4096;
 
+// A tick that was enqueued and may still run: its event, the requests whose
+// last step it holds (retired once it completes), and the pinned copy of the
+// status words it reads back.
+struct EngTick {
+    bool busy = false;
+    uint64_t seq = 0;
+    hipEvent_t ev = nullptr;
+    unsigned *hflags = nullptr;  // pinned host memory, kEngSlots words
+    std::vector<EngReq> finishing;
+};
+
 }  // namespace
 
 struct ks_engine {
     char *ws;
     size_t region_bytes;   // [0, region_bytes): request regions
-    size_t tab_off, tab_bytes;
+    size_t tab_off, tab_bytes;  // two table buffers of tab_bytes each (ticks alternate)
     unsigned *dflags;      // kEngSlots status words
     hipStream_t stream;
     std::map<size_t, size_t> free_list;  // offset -> bytes
     std::set<int32_t> free_slots;
-    std::vector<EngReq> inflight;
+    std::vector<EngReq> inflight;        // requests with steps still to launch
     std::vector<std::pair<uint64_t, ks_status>> retired;
-    size_t tab_used;       // sum of tab_need over in-flight requests
+    size_t tab_used;       // sum of tab_need over requests with steps still to launch
     uint64_t next_ticket, ticks;
     std::vector<char> staging;
-    std::vector<unsigned> hflags;
+    EngTick tick[2];       // the tick using table buffer b
+    int next_buf;          // table buffer of the next tick
     SideStreams side;      // the launch groups of one tick are independent
 };
 
@@ -1424,6 +1518,42 @@ ks_status status_of(unsigned f) {
          : (f & ks::FLAG_RANK) ? KS_E_RANK : KS_OK;
 }
 
+// Retire the requests of completed ticks, oldest tick first: status from the
+// tick's copy of the status words; region and status word free again.  With
+// wait, blocks until every enqueued tick has completed.  Returns how many
+// requests were retired, or -1 on a HIP error.
+int32_t eng_reap(ks_engine *e, bool wait) {
+    int32_t nfin = 0;
+    while (true) {
+        EngTick *T = nullptr;
+        for (auto &t : e->tick)
+            if (t.busy && (!T || t.seq < T->seq)) T = &t;
+        if (!T) return nfin;
+        if (wait) {
+            if (hipEventSynchronize(T->ev) != hipSuccess) return -1;
+        } else {
+            const hipError_t q = hipEventQuery(T->ev);
+            if (q == hipErrorNotReady) {
+                (void)hipGetLastError();
+                return nfin;
+            }
+            if (q != hipSuccess) return -1;
+        }
+        for (const EngReq &r : T->finishing) {
+            e->retired.emplace_back(r.ticket, status_of(T->hflags[r.slot]));
+            eng_free(e, r.pr.ws_off, align_up(r.pr.lo.total));
+            e->free_slots.insert(r.slot);
+            ++nfin;
+        }
+        T->finishing.clear();
+        T->busy = false;
+    }
+}
+
+size_t eng_finishing(const ks_engine *e) {
+    return e->tick[0].finishing.size() + e->tick[1].finishing.size();
+}
+
 }  // namespace
 
 extern "C" {
@@ -1438,19 +1568,19 @@ ks_status ks_engine_create(void *workspace, size_t ws_bytes, void *hip_stream, k
     if (!e) return KS_E_ARG;
     e->ws = static_cast<char *>(workspace);
     e->stream = static_cast<hipStream_t>(hip_stream);
-    // 1/16 of the workspace (at least 256 KiB) for launch tables, the status
-    // words after them, the rest for request regions
-    size_t tab = std::max<size_t>((size_t)256 << 10, ws_bytes / 16) / kAlign * kAlign;
+    // 1/16 of the workspace (at least 256 KiB) for two launch-table buffers,
+    // the status words after them, the rest for request regions
+    size_t tab = std::max<size_t>((size_t)256 << 10, ws_bytes / 16) / (2 * kAlign) * (2 * kAlign);
     e->region_bytes = (ws_bytes - tab - flags_bytes) / kAlign * kAlign;
     e->tab_off = e->region_bytes;
-    e->tab_bytes = tab;
+    e->tab_bytes = tab / 2;
     e->dflags = reinterpret_cast<unsigned *>(e->ws + e->tab_off + tab);
+    e->next_buf = 0;
     e->free_list[0] = e->region_bytes;
     for (int32_t s = 0; s < kEngSlots; ++s) e->free_slots.insert(s);
     e->tab_used = kEngTabFixed;
     e->next_ticket = 1;
     e->ticks = 0;
-    e->hflags.assign(kEngSlots, 0u);
     e->side.create();
     *out = e;
     return KS_OK;
@@ -1503,7 +1633,35 @@ ks_status ks_engine_submit(ks_engine *e, const ks_desc *desc, const ks_io *io, i
 ks_status ks_engine_step(ks_engine *e, int32_t *finished) {
     if (!e) return KS_E_ARG;
     if (finished) *finished = 0;
-    if (e->inflight.empty()) return KS_OK;
+    int32_t nfin = eng_reap(e, false);
+    if (nfin < 0) return KS_E_HIP;
+    if (e->inflight.empty()) {
+        if (finished) *finished = nfin;
+        return KS_OK;
+    }
+    if (!e->tick[0].ev) {  // first tick: events and pinned status copies
+        for (auto &t : e->tick) {
+            if (hipEventCreateWithFlags(&t.ev, hipEventDisableTiming) != hipSuccess ||
+                hipHostMalloc(reinterpret_cast<void **>(&t.hflags), sizeof(unsigned) * kEngSlots,
+                              hipHostMallocDefault) != hipSuccess) {
+                (void)hipGetLastError();
+                for (auto &u : e->tick) {
+                    if (u.ev) (void)hipEventDestroy(u.ev);
+                    if (u.hflags) (void)hipHostFree(u.hflags);
+                    u.ev = nullptr;
+                    u.hflags = nullptr;
+                }
+                return KS_E_HIP;
+            }
+        }
+    }
+    EngTick &T = e->tick[e->next_buf];
+    if (T.busy) {  // both table buffers in use: wait for the older tick (this one)
+        if (hipEventSynchronize(T.ev) != hipSuccess) return KS_E_HIP;
+        const int32_t more = eng_reap(e, false);
+        if (more < 0) return KS_E_HIP;
+        nfin += more;
+    }
     const size_t R = e->inflight.size();
     std::vector<ks::FwdArgs> ftab;
     std::vector<ks::FwdTailArgs> ttab;
@@ -1599,7 +1757,7 @@ ks_status ks_engine_step(ks_engine *e, int32_t *finished) {
     put(o_k, blk.data(), sizeof(int64_t) * blk.size());
     put(o_l, level.data(), sizeof(int32_t) * level.size());
     put(o_c, clear.data(), sizeof(int32_t) * clear.size());
-    char *dt = e->ws + e->tab_off;
+    char *dt = e->ws + e->tab_off + (size_t)e->next_buf * e->tab_bytes;
     if (hipMemcpyAsync(dt, st, off, hipMemcpyHostToDevice, e->stream) != hipSuccess) return KS_E_HIP;
     if (!clear.empty())
         ks::launch_clear_flags_list(e->dflags, reinterpret_cast<const int32_t *>(dt + o_c), (int32_t)clear.size(),
@@ -1642,45 +1800,45 @@ ks_status ks_engine_step(ks_engine *e, int32_t *finished) {
     }
     if (fork) e->side.join(e->stream);
     if (hipGetLastError() != hipSuccess) return KS_E_HIP;
-    // advance; read the status words of the requests that finish
-    std::vector<char> fin(R, 0);
+    // advance; the requests whose last step this tick holds wait (in the
+    // tick) for its completion, with a copy of the status words
     int32_t hi = -1;
+    std::vector<EngReq> keep;
+    keep.reserve(R);
     for (size_t q = 0; q < R; ++q) {
         EngReq &r = e->inflight[q];
         r.fresh = false;
-        if (!eng_advance(r)) {
-            fin[q] = 1;
-            hi = std::max(hi, r.slot);
-        }
-    }
-    if (hi >= 0 && hipMemcpyAsync(e->hflags.data(), e->dflags, sizeof(unsigned) * (hi + 1), hipMemcpyDeviceToHost,
-                                  e->stream) != hipSuccess)
-        return KS_E_HIP;
-    if (hipStreamSynchronize(e->stream) != hipSuccess) return KS_E_HIP;
-    ++e->ticks;
-    std::vector<EngReq> keep;
-    keep.reserve(R);
-    int32_t nfin = 0;
-    for (size_t q = 0; q < R; ++q) {
-        EngReq &r = e->inflight[q];
-        if (!fin[q]) {
+        if (eng_advance(r)) {
             keep.push_back(r);
             continue;
         }
-        e->retired.emplace_back(r.ticket, status_of(e->hflags[r.slot]));
-        eng_free(e, r.pr.ws_off, align_up(r.pr.lo.total));
-        e->free_slots.insert(r.slot);
-        e->tab_used -= r.tab_need;
-        ++nfin;
+        hi = std::max(hi, r.slot);
+        e->tab_used -= r.tab_need;  // no later tick holds it
+        T.finishing.push_back(r);
     }
     e->inflight.swap(keep);
+    if (hi >= 0 && hipMemcpyAsync(T.hflags, e->dflags, sizeof(unsigned) * (hi + 1), hipMemcpyDeviceToHost,
+                                  e->stream) != hipSuccess)
+        return KS_E_HIP;
+    if (hipEventRecord(T.ev, e->stream) != hipSuccess) return KS_E_HIP;
+    T.busy = true;
+    T.seq = ++e->ticks;
+    e->next_buf ^= 1;
     if (finished) *finished = nfin;
     return KS_OK;
+}
+
+ks_status ks_engine_wait(ks_engine *e, int32_t *finished) {
+    if (!e) return KS_E_ARG;
+    const int32_t nfin = eng_reap(e, true);
+    if (finished) *finished = nfin < 0 ? 0 : nfin;
+    return nfin < 0 ? KS_E_HIP : KS_OK;
 }
 
 ks_status ks_engine_retired(ks_engine *e, int32_t capacity, uint64_t *tickets, ks_status *statuses,
                             int32_t *count) {
     if (!e || !count || capacity < 0 || (capacity > 0 && (!tickets || !statuses))) return KS_E_ARG;
+    if (eng_reap(e, false) < 0) return KS_E_HIP;
     const int32_t c = (int32_t)std::min<size_t>((size_t)capacity, e->retired.size());
     for (int32_t i = 0; i < c; ++i) {
         tickets[i] = e->retired[i].first;
@@ -1693,6 +1851,7 @@ ks_status ks_engine_retired(ks_engine *e, int32_t capacity, uint64_t *tickets, k
 
 ks_status ks_engine_poll(ks_engine *e, uint64_t ticket, ks_status *result) {
     if (!e || !result) return KS_E_ARG;
+    if (eng_reap(e, false) < 0) return KS_E_HIP;
     for (size_t i = 0; i < e->retired.size(); ++i) {
         if (e->retired[i].first != ticket) continue;
         *result = e->retired[i].second;
@@ -1701,15 +1860,19 @@ ks_status ks_engine_poll(ks_engine *e, uint64_t ticket, ks_status *result) {
     }
     for (const EngReq &r : e->inflight)
         if (r.ticket == ticket) return KS_E_BUSY;
+    for (const auto &t : e->tick)
+        for (const EngReq &r : t.finishing)
+            if (r.ticket == ticket) return KS_E_BUSY;
     return KS_E_ARG;
 }
 
 ks_status ks_engine_query(const ks_engine *e, ks_engine_stats *out) {
     if (!e || !out) return KS_E_ARG;
     std::memset(out, 0, sizeof(*out));
-    out->inflight = (int64_t)e->inflight.size();
+    out->inflight = (int64_t)(e->inflight.size() + eng_finishing(e));
     out->retired_pending = (int64_t)e->retired.size();
     out->ticks = (int64_t)e->ticks;
+    out->ticks_pending = (int64_t)e->tick[0].busy + (int64_t)e->tick[1].busy;
     out->region_bytes = e->region_bytes;
     for (auto &f : e->free_list) {
         out->free_bytes += f.second;
@@ -1720,7 +1883,12 @@ ks_status ks_engine_query(const ks_engine *e, ks_engine_stats *out) {
 
 ks_status ks_engine_destroy(ks_engine *e) {
     if (!e) return KS_E_ARG;
+    if (e->tick[0].ev) (void)hipStreamSynchronize(e->stream);  // no tick reads the tables or pinned words
     e->side.destroy(e->stream);
+    for (auto &t : e->tick) {
+        if (t.ev) (void)hipEventDestroy(t.ev);
+        if (t.hflags) (void)hipHostFree(t.hflags);
+    }
     delete e;
     return KS_OK;
 }

@@ -27,7 +27,7 @@ SYMBOLS = ("ks_workspace_bytes", "ks_supported", "ks_create", "ks_smooth", "ks_c
            "ks_smooth_cov", "ks_destroy", "ks_status_string", "ks_plan_layout",
            "ks_time_kernels", "ks_kernel_time", "ks_batch_workspace_bytes", "ks_batch_create",
            "ks_batch_smooth", "ks_batch_destroy", "ks_engine_create", "ks_engine_submit",
-           "ks_engine_step", "ks_engine_retired", "ks_engine_poll", "ks_engine_query", "ks_engine_destroy",
+           "ks_engine_step", "ks_engine_wait", "ks_engine_retired", "ks_engine_poll", "ks_engine_query", "ks_engine_destroy",
            "ks_set_tuning", "ks_get_tuning", "ks_plan_schedule", "ks_smooth_cov_lag1", "ks_objective",
            "ks_smooth_cov_static")
 KS_TIME_OFF, KS_TIME_FWD_LEVEL0, KS_TIME_BWD_LEVEL0, KS_TIME_FWD_ALL, KS_TIME_BWD_ALL = range(5)
@@ -37,6 +37,18 @@ class Desc(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int64), ("n", ctypes.c_int32), ("m", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("K_layout", ctypes.c_int32),
                 ("C_layout", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("fwd_tail_passes", ctypes.c_int32), ("bwd_tail_passes", ctypes.c_int32),
+                ("fp32_switch_columns", ctypes.c_int64), ("fwd_group", ctypes.c_int32),
+                ("fwd_group_from", ctypes.c_int32), ("bwd_group", ctypes.c_int32),
+                ("bwd_group_from", ctypes.c_int32)]
+
+
+TUNING_KEYS = tuple(f for f, _t in Tuning._fields_)
+TUNING_DEFAULTS = dict(fwd_tail_passes=2, bwd_tail_passes=2, fp32_switch_columns=1024, fwd_group=1,
+                       fwd_group_from=1, bwd_group=1, bwd_group_from=1)
 
 
 class Layout(ctypes.Structure):
@@ -52,7 +64,7 @@ class Io(ctypes.Structure):
 class EngineStats(ctypes.Structure):
     _fields_ = [("inflight", ctypes.c_int64), ("retired_pending", ctypes.c_int64), ("ticks", ctypes.c_int64),
                 ("region_bytes", ctypes.c_size_t), ("free_bytes", ctypes.c_size_t),
-                ("largest_free", ctypes.c_size_t)]
+                ("largest_free", ctypes.c_size_t), ("ticks_pending", ctypes.c_int64)]
 
 
 class KsError(RuntimeError):
@@ -117,6 +129,8 @@ def lib():
                                    ctypes.POINTER(ctypes.c_uint64)]
     L.ks_engine_step.restype = ctypes.c_int
     L.ks_engine_step.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    L.ks_engine_wait.restype = ctypes.c_int
+    L.ks_engine_wait.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     L.ks_engine_retired.restype = ctypes.c_int
     L.ks_engine_retired.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64),
                                     ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int32)]
@@ -127,10 +141,9 @@ def lib():
     L.ks_engine_destroy.restype = ctypes.c_int
     L.ks_engine_destroy.argtypes = [vp]
     L.ks_set_tuning.restype = ctypes.c_int
-    L.ks_set_tuning.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64]
+    L.ks_set_tuning.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Tuning)]
     L.ks_get_tuning.restype = ctypes.c_int
-    L.ks_get_tuning.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
-                                ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64)]
+    L.ks_get_tuning.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(Tuning)]
     L.ks_plan_schedule.restype = ctypes.c_int
     L.ks_plan_schedule.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                    ctypes.POINTER(ctypes.c_int32)]
@@ -144,20 +157,26 @@ def lib():
     return L
 
 
-def set_tuning(n: int, fp32: bool, fwd_tail_passes: int, bwd_tail_passes: int, fp32_switch_columns: int = 1024):
-    st = lib().ks_set_tuning(int(n), KS_FP32_FORM if fp32 else KS_FP64, int(fwd_tail_passes),
-                             int(bwd_tail_passes), int(fp32_switch_columns))
+def set_tuning(n: int, fp32: bool, **values):
+    """Set the schedule choices of (n, form); keys of TUNING_KEYS, missing ones
+    keep their current value."""
+    cur = get_tuning(n, fp32)
+    unknown = set(values) - set(TUNING_KEYS)
+    if unknown:
+        raise ValueError(f"unknown tuning keys {sorted(unknown)}")
+    cur.update(values)
+    t = Tuning(**{k: int(cur[k]) for k in TUNING_KEYS})
+    st = lib().ks_set_tuning(int(n), KS_FP32_FORM if fp32 else KS_FP64, ctypes.byref(t))
     if st != KS_OK:
         raise KsError(st, "ks_set_tuning")
 
 
 def get_tuning(n: int, fp32: bool = False) -> dict:
-    f, b, w = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
-    st = lib().ks_get_tuning(int(n), KS_FP32_FORM if fp32 else KS_FP64, ctypes.byref(f), ctypes.byref(b),
-                             ctypes.byref(w))
+    t = Tuning()
+    st = lib().ks_get_tuning(int(n), KS_FP32_FORM if fp32 else KS_FP64, ctypes.byref(t))
     if st != KS_OK:
         raise KsError(st, "ks_get_tuning")
-    return dict(fwd_tail_passes=f.value, bwd_tail_passes=b.value, fp32_switch_columns=w.value)
+    return {k: getattr(t, k) for k in TUNING_KEYS}
 
 
 def load_tuning(path: str) -> int:
@@ -166,8 +185,8 @@ def load_tuning(path: str) -> int:
     with open(path) as fh:
         table = json.load(fh)
     for e in table.get("entries", []):
-        set_tuning(e["n"], e["form"] == "fp32", e["fwd_tail_passes"], e["bwd_tail_passes"],
-                   e.get("fp32_switch_columns", 1024))
+        vals = {k: e.get(k, TUNING_DEFAULTS[k]) for k in TUNING_KEYS}
+        set_tuning(e["n"], e["form"] == "fp32", **vals)
     return len(table.get("entries", []))
 
 
@@ -532,13 +551,9 @@ class Engine:
         self._live[t.value] = (inputs, u, cov)
         return t.value
 
-    def step(self):
-        fin = ctypes.c_int32()
-        st = lib().ks_engine_step(self._h, ctypes.byref(fin))
-        if st != KS_OK:
-            raise KsError(st, "ks_engine_step")
+    def _collect(self, fin):
         out = []
-        cap = max(int(fin.value), 1)
+        cap = max(int(fin), 1)
         tickets = (ctypes.c_uint64 * cap)()
         statuses = (ctypes.c_int * cap)()
         while True:
@@ -551,6 +566,24 @@ class Engine:
                 out.append((int(tickets[i]), int(statuses[i])))
             if cnt.value < cap:
                 return out
+
+    def step(self):
+        """Enqueue one tick (asynchronous) and return the (ticket, status)
+        pairs of the requests retired meanwhile."""
+        fin = ctypes.c_int32()
+        st = lib().ks_engine_step(self._h, ctypes.byref(fin))
+        if st != KS_OK:
+            raise KsError(st, "ks_engine_step")
+        return self._collect(fin.value)
+
+    def wait(self):
+        """Block until every enqueued tick has completed; returns the retired
+        (ticket, status) pairs."""
+        fin = ctypes.c_int32()
+        st = lib().ks_engine_wait(self._h, ctypes.byref(fin))
+        if st != KS_OK:
+            raise KsError(st, "ks_engine_wait")
+        return self._collect(fin.value)
 
     def stats(self) -> dict:
         s = EngineStats()

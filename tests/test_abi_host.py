@@ -170,25 +170,45 @@ def test_tuning_table_drives_the_schedule(monkeypatch):
     try:
         k, n = 100000, 5  # a class with the wavefront-family backward tail
         L = (k + 1).bit_length() - 1
-        ks.set_tuning(n, False, 0, 0, 1024)
-        assert ks.get_tuning(n, False) == dict(fwd_tail_passes=0, bwd_tail_passes=0, fp32_switch_columns=1024)
+        ks.set_tuning(n, False, **dict(ks.TUNING_DEFAULTS, fwd_tail_passes=0, bwd_tail_passes=0))
+        assert ks.get_tuning(n, False) == dict(ks.TUNING_DEFAULTS, fwd_tail_passes=0, bwd_tail_passes=0)
         assert _fake_plan(k, n, 3) == (0, L, L + 1)          # base level only, no backward tail
-        ks.set_tuning(n, False, 10**6, 10**6, 1024)
+        ks.set_tuning(n, False, fwd_tail_passes=10**6, bwd_tail_passes=10**6)
         assert _fake_plan(k, n, 3) == (0, 0, 0)              # everything in the tails
-        ks.set_tuning(n, True, 2, 2, 4096)
+        ks.set_tuning(n, True, **dict(ks.TUNING_DEFAULTS, fp32_switch_columns=4096))
         fp32_levels = sum(1 for l in range(L) if (k + 1) >> l > 4096)
         lev, l0, l1 = _fake_plan(k, n, 3, fp32=True)
         assert lev == fp32_levels and l0 > lev and l1 >= lev
         monkeypatch.setenv("KS_TAIL_PASSES", "0")
         assert _fake_plan(k, n, 3)[1:] == (L, L + 1)
         with pytest.raises(ks.KsError):
-            ks.set_tuning(0, False, 1, 1, 1024)
+            ks.set_tuning(0, False, fwd_tail_passes=1)
         with pytest.raises(ks.KsError):
-            ks.set_tuning(5, False, -1, 1, 1024)
+            ks.set_tuning(5, False, fwd_tail_passes=-1)
     finally:
         monkeypatch.delenv("KS_TAIL_PASSES", raising=False)
         for fp32, e in zip((False, True), saved):
-            ks.set_tuning(5, fp32, e["fwd_tail_passes"], e["bwd_tail_passes"], e["fp32_switch_columns"])
+            ks.set_tuning(5, fp32, **e)
+
+
+def test_level_groups_tuning_round_trip(monkeypatch):
+    """Level-group choices are stored per (n, form), validated, and the
+    environment overrides them."""
+    for v in ("KS_FWD_GROUP", "KS_FWD_GROUP_FROM", "KS_BWD_GROUP", "KS_BWD_GROUP_FROM"):
+        monkeypatch.delenv(v, raising=False)
+    saved = ks.get_tuning(6, False)
+    try:
+        ks.set_tuning(6, False, fwd_group=4, fwd_group_from=1, bwd_group=3, bwd_group_from=2)
+        t = ks.get_tuning(6, False)
+        assert (t["fwd_group"], t["fwd_group_from"], t["bwd_group"], t["bwd_group_from"]) == (4, 1, 3, 2)
+        monkeypatch.setenv("KS_FWD_GROUP", "2")
+        assert ks.get_tuning(6, False)["fwd_group"] == 2
+        for bad in (dict(fwd_group=0), dict(fwd_group=9), dict(bwd_group=0), dict(bwd_group_from=-1)):
+            with pytest.raises(ks.KsError):
+                ks.set_tuning(6, False, **bad)
+    finally:
+        monkeypatch.delenv("KS_FWD_GROUP", raising=False)
+        ks.set_tuning(6, False, **saved)
 
 
 def test_static_entry_rejects_oversized_and_invalid_problems():

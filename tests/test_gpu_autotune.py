@@ -27,7 +27,7 @@ def test_tune_one_entry_keeps_results():
     p = gen.make_problem(np.random.default_rng(5), 3000, n, 3, cov="dense")
     saved = ks.get_tuning(n, False)
     try:
-        ks.set_tuning(n, False, 2, 2, 1024)
+        ks.set_tuning(n, False, **ks.TUNING_DEFAULTS)
         u0, S0 = smooth(p)
         e = autotune.tune_one(n, False, reps=2)
         assert e["fwd_tail_passes"] in autotune.PASSES and e["bwd_tail_passes"] in autotune.PASSES
@@ -38,7 +38,7 @@ def test_tune_one_entry_keeps_results():
         ref = seq.smooth(p)
         assert np.max(np.abs(u1 - ref["u"])) / np.max(np.abs(ref["u"])) < 1e-10
     finally:
-        ks.set_tuning(n, False, saved["fwd_tail_passes"], saved["bwd_tail_passes"], saved["fp32_switch_columns"])
+        ks.set_tuning(n, False, **saved)
 
 
 def test_committed_table_is_complete_and_loads():

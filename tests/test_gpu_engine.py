@@ -42,6 +42,7 @@ def serve(reqs, ws_bytes):
     ticks in flight) and the number of refusals."""
     eng = ks.Engine(ws_bytes)
     outs, tick_of, done, refused = {}, {}, {}, 0
+    during = 0  # submissions made while an earlier tick was still in flight
     pending = list(range(len(reqs)))
     tick = 0
     while pending or eng.stats()["inflight"]:
@@ -55,11 +56,14 @@ def serve(reqs, ws_bytes):
             u = torch.empty((p.k + 1, p.n), dtype=torch.float64, device="cuda")
             S = torch.empty((p.k + 1, p.n, p.n), dtype=torch.float64, device="cuda") if r["cov"] else None
             shape = (p.k, p.n, p.m, p.K_diag, p.C_diag, r["fp32"])
-            t = eng.submit(shape, ks.to_device(p), u, S)
+            args = ks.to_device(p)
+            busy = eng.stats()["ticks_pending"] > 0
+            t = eng.submit(shape, args, u, S)
             if t is None:
                 refused += 1
                 still.append(i)
                 continue
+            during += busy
             outs[t] = (i, u, S)
             tick_of[t] = tick
         pending = still
@@ -69,10 +73,11 @@ def serve(reqs, ws_bytes):
         tick += 1
         assert tick < 10000
     assert not outs
+    assert eng.wait() == []
     stats = eng.stats()
-    assert stats["free_bytes"] == stats["region_bytes"]
+    assert stats["free_bytes"] == stats["region_bytes"] and stats["ticks_pending"] == 0
     eng.close()
-    return done, refused
+    return done, refused, during
 
 
 def check_against_alone(reqs, done):
@@ -87,7 +92,8 @@ def check_against_alone(reqs, done):
 
 def test_engine_mixed_arrivals_equal_alone_and_oracle():
     reqs = requests()
-    done, _ = serve(reqs, 256 << 20)
+    done, _, during = serve(reqs, 256 << 20)
+    assert during > 0  # ticks are asynchronous: requests were admitted while others ran on the GPU
     check_against_alone(reqs, done)
     for i, r in enumerate(reqs):
         if r["fp32"]:
@@ -109,7 +115,7 @@ def test_engine_admission_under_pressure():
     need = max(ks.Engine.footprint((r["p"].k, r["p"].n, r["p"].m, r["p"].K_diag, r["p"].C_diag, r["fp32"]))
                for r in reqs)
     ws = max(2 * need, 1 << 20) * 16 // 15 + (1 << 16)
-    done, refused = serve(reqs, ws)
+    done, refused, _ = serve(reqs, ws)
     assert refused > 0
     check_against_alone(reqs, done)
 
@@ -130,6 +136,8 @@ def test_engine_statuses_per_request():
         keep[t] = i
     while eng.stats()["inflight"]:
         for t, st in eng.step():
+            status[keep[t]] = st
+        for t, st in eng.wait():  # the blocking form retires the same way
             status[keep[t]] = st
     eng.close()
     assert [status[i] for i in range(len(reqs) - 1)] == [ks.KS_OK] * (len(reqs) - 1)
