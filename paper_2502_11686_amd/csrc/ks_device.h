@@ -49,6 +49,11 @@ namespace ks {
 
 enum Role { CUR = 0, RIGHT = 1, RHS = 2, LEFT = 3, IDLE = 4, BRIGHT = 5, BRHS = 6 };
 
+// Minimum wavefronts per SIMD the forward level kernels are compiled for: at
+// n = 6 a unit's stacks need about 130 VGPRs unconstrained (three wavefronts
+// per SIMD), at 128 a fourth fits (n = 8 would spill heavily).
+constexpr int wf_min_waves(int n) { return n >= 4 && n <= 6 ? 4 : 1; }
+
 template <int N>
 struct Geo {
     static constexpr int G = 3 * N + 1;             // lanes per unit
@@ -149,12 +154,18 @@ __device__ __forceinline__ double rsq_nr(double d) {
 // reflector to its own column (the pivot lane too); the pivot diagonal is then
 // set to beta and, at the end, the strictly lower parts of the pivot columns
 // are set to zero.
-template <int H, int NP, class T>
+// TT > 0: rows 0..TT-1 form an upper-triangular block in the pivot columns
+// (row r is zero in pivot columns q < r).  Reflector p then has zeros in rows
+// p+1..TT-1, and leaves them (and the triangle) as they are, so it is formed
+// and applied over rows p and TT..H-1 only: the same reflector as the dense
+// loop, with the known zeros skipped.
+template <int H, int NP, class T, int TT = 0>
 __device__ __forceinline__ void hqr(T (&x)[H], int gl, int gbase, int pl0) {
     constexpr int P = NP < H ? NP : H;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
         const int src = gbase + pl0 + p;
+        const int r0 = p + 1 > TT ? p + 1 : TT;  // first row below the pivot that may be nonzero
         const T alpha = x[p];
         T s0 = 0, s1 = 0, sc = 1, am = 1, as = alpha;
         if constexpr (sizeof(T) == 4) {
@@ -162,18 +173,18 @@ __device__ __forceinline__ void hqr(T (&x)[H], int gl, int gbase, int pl0) {
             // (no overflow or underflow for any representable column)
             am = fabs(alpha);
 #pragma unroll
-            for (int r = p + 1; r < H; ++r) am = fmax(am, fabs(x[r]));
+            for (int r = r0; r < H; ++r) am = fmax(am, fabs(x[r]));
             sc = am > T(0) ? rcp_nr(am) : T(0);
             as = alpha * sc;
 #pragma unroll
-            for (int r = p + 1; r < H; r += 2) s0 = fma(x[r] * sc, x[r] * sc, s0);
+            for (int r = r0; r < H; r += 2) s0 = fma(x[r] * sc, x[r] * sc, s0);
 #pragma unroll
-            for (int r = p + 2; r < H; r += 2) s1 = fma(x[r] * sc, x[r] * sc, s1);
+            for (int r = r0 + 1; r < H; r += 2) s1 = fma(x[r] * sc, x[r] * sc, s1);
         } else {
 #pragma unroll
-            for (int r = p + 1; r < H; r += 2) s0 = fma(x[r], x[r], s0);
+            for (int r = r0; r < H; r += 2) s0 = fma(x[r], x[r], s0);
 #pragma unroll
-            for (int r = p + 2; r < H; r += 2) s1 = fma(x[r], x[r], s1);
+            for (int r = r0 + 1; r < H; r += 2) s1 = fma(x[r], x[r], s1);
         }
         const T xn2 = s0 + s1;                       // scaled by sc^2 in FP32
         const T s = fma(as, as, xn2);
@@ -187,16 +198,16 @@ __device__ __forceinline__ void hqr(T (&x)[H], int gl, int gbase, int pl0) {
         const T v0b = bperm(v0, src);
         T v[H];
 #pragma unroll
-        for (int r = p + 1; r < H; ++r) v[r] = bperm(x[r], src);
+        for (int r = r0; r < H; ++r) v[r] = bperm(x[r], src);
         T w0 = v0b * x[p], w1 = 0;
 #pragma unroll
-        for (int r = p + 1; r < H; r += 2) w0 = fma(v[r], x[r], w0);
+        for (int r = r0; r < H; r += 2) w0 = fma(v[r], x[r], w0);
 #pragma unroll
-        for (int r = p + 2; r < H; r += 2) w1 = fma(v[r], x[r], w1);
+        for (int r = r0 + 1; r < H; r += 2) w1 = fma(v[r], x[r], w1);
         const T w = (w0 + w1) * cb;
         x[p] = (gl == pl0 + p) ? dnew : fma(-w, v0b, x[p]);
 #pragma unroll
-        for (int r = p + 1; r < H; ++r) x[r] = fma(-w, v[r], x[r]);
+        for (int r = r0; r < H; ++r) x[r] = fma(-w, v[r], x[r]);
     }
     const unsigned q = (unsigned)(gl - pl0);
 #pragma unroll
@@ -421,24 +432,24 @@ __device__ __forceinline__ void fold_part(const FwdArgs &a, int64_t t, int gl, i
     constexpr int HC = 2 * N;
     // the last column jl = N_l - 1 (even, no right neighbour)
     const int64_t jl = a.Nl - 1;
+    // C2 = [R~ (its observation block, triangular) ; E+ | E- | eta]
     T A2[RO], C2[HC];
-#pragma unroll
-    for (int r = N; r < HC; ++r) C2[r] = T(0);
     if constexpr (RAW) {
         T cvO[MM], cvE[N];
         load_obs_raw<N, MM>(A2, 0, cvO, jl, L, gl, CUR, 0, a, true);
-        load_evol_raw<N>(C2, 0, cvE, jl, L, gl, LEFT, CUR, 2 * N + 1, a, true);
+        load_evol_raw<N>(C2, N, cvE, jl, L, gl, LEFT, CUR, 2 * N + 1, a, true);
         whiten<RO, MM>(a.C_diag, A2, 0, cvO, gl, gb, 0, bad);
-        whiten<HC, N>(a.K_diag, C2, 0, cvE, gl, gb, 2 * N + 1, bad);
+        whiten<HC, N>(a.K_diag, C2, N, cvE, gl, gb, 2 * N + 1, bad);
+        hqr<RO, N>(A2, gl, gb, 0);
     } else {
+        // a reduced observation block is already triangular
         const TIN *rec = slot<TIN>(a.sys_in, jl, GE::SREC);
         load_obs_sys<N>(A2, 0, rec, L, CUR, true);
-        load_evol_sys<N>(C2, 0, rec + GE::OREC, L, LEFT, CUR, true);
+        load_evol_sys<N>(C2, N, rec + GE::OREC, L, LEFT, CUR, true);
     }
-    hqr<RO, N>(A2, gl, gb, 0);
 #pragma unroll
-    for (int r = 0; r < N; ++r) C2[N + r] = r < RO ? A2[r] : T(0);
-    hqr<HC, N>(C2, gl, gb, 0);
+    for (int r = 0; r < N; ++r) C2[r] = r < RO ? A2[r] : T(0);
+    hqr<HC, N, T, N>(C2, gl, gb, 0);
     store_rrow<N>(slot<T>(a.rrows, t + 1, GE::RREC), C2, gl, true);
     diag_stats<N>(C2, L, true, dmin, dmax, nonfinite);
     // Z rows (left lanes) move onto the right lanes; rhs keeps zeta
@@ -450,7 +461,7 @@ __device__ __forceinline__ void fold_part(const FwdArgs &a, int64_t t, int gl, i
         B2[r] = Onew[r];
         B2[N + r] = (L.role == RIGHT || L.role == RHS) ? z : T(0);
     }
-    hqr<2 * N, N>(B2, gl, gb, N);
+    hqr<2 * N, N, T, N>(B2, gl, gb, N);
 #pragma unroll
     for (int r = 0; r < N; ++r) Onew[r] = B2[r];
 }
@@ -471,41 +482,54 @@ __device__ __forceinline__ void fwd_unit(const FwdArgs &a, int64_t t, bool in, i
     const int64_t j = 2 * t;
     const bool fold = valid && (a.Nl & 1) && t == a.units - 1;
 
-    // A = [O_j | 0 | w_j ; E-_{j+1} | E+_{j+1} | eta_{j+1}]      (cur, right, rhs lanes)
-    // B = [D~_{j+1} | gamma ; O_{j+1} | w_{j+1}]                  (right, rhs lanes)
-    // C = [E+_j | 0 | eta_j | E-_j ; R~_j | X_j | rho~_j | 0]     (cur, right, rhs, left lanes)
+    // Above level 0:
+    //   A = [O_j | 0 | w_j ; E-_{j+1} | E+_{j+1} | eta_{j+1}]      (cur, right, rhs lanes)
+    //   B = [O_{j+1} | w_{j+1} ; D~_{j+1} | gamma]                  (right, rhs lanes)
+    //   C = [R~_j | X_j | rho~_j | 0 ; E+_j | 0 | eta_j | E-_j]     (cur, right, rhs, left lanes)
+    // where the observation blocks O_j, O_{j+1} are triangular (from the level
+    // below's step 3) and R~_j is: each stack starts with a triangular block
+    // whose known zeros the reflectors skip.  At level 0 (raw, whitened
+    // inputs; no triangular observation block) B and C hold the same blocks
+    // in the order [D~; O] and [E; R~] with dense reflectors, which keeps the
+    // kernel within 128 VGPRs.
+    constexpr int OB = RAW ? RO : 0;   // first row of O_{j+1} in B
+    constexpr int DB = RAW ? 0 : RO;   // first row of D~_{j+1} in B
+    constexpr int EC = RAW ? 0 : N;    // first row of the evolution block in C
+    constexpr int RC = RAW ? N : 0;    // first row of R~_j in C
+    constexpr int TO = RAW ? 0 : N;
+    constexpr int TC = RAW ? 0 : N;
     T A[HA], B[HB], C[HC];
-#pragma unroll
-    for (int r = N; r < HC; ++r) C[r] = T(0);
     if constexpr (RAW) {
+#pragma unroll
+        for (int r = N; r < HC; ++r) C[r] = T(0);
         T cvOa[MM], cvOb[MM], cvEa[N], cvEc[N];
         load_obs_raw<N, MM>(A, 0, cvOa, j, L, gl, CUR, 0, a, valid);
         load_evol_raw<N>(A, RO, cvEa, j + 1, L, gl, CUR, RIGHT, 0, a, valid);
-        load_obs_raw<N, MM>(B, RO, cvOb, j + 1, L, gl, RIGHT, N, a, valid);
-        load_evol_raw<N>(C, 0, cvEc, j, L, gl, LEFT, CUR, 2 * N + 1, a, valid && j >= 1);
+        load_obs_raw<N, MM>(B, OB, cvOb, j + 1, L, gl, RIGHT, N, a, valid);
+        load_evol_raw<N>(C, EC, cvEc, j, L, gl, LEFT, CUR, 2 * N + 1, a, valid && j >= 1);
         whiten<HA, MM>(a.C_diag, A, 0, cvOa, gl, gb, 0, bad);
         whiten<HA, N>(a.K_diag, A, RO, cvEa, gl, gb, 0, bad);
-        whiten<HB, MM>(a.C_diag, B, RO, cvOb, gl, gb, N, bad);
-        whiten<HC, N>(a.K_diag, C, 0, cvEc, gl, gb, 2 * N + 1, bad);
+        whiten<HB, MM>(a.C_diag, B, OB, cvOb, gl, gb, N, bad);
+        whiten<HC, N>(a.K_diag, C, EC, cvEc, gl, gb, 2 * N + 1, bad);
     } else {
         const TIN *rec = slot<TIN>(a.sys_in, j, GE::SREC);
         load_obs_sys<N>(A, 0, rec, L, CUR, valid);
         const TIN *rec1 = slot<TIN>(a.sys_in, j + 1, GE::SREC);
         load_evol_sys<N>(A, RO, rec1 + GE::OREC, L, CUR, RIGHT, valid);
-        load_obs_sys<N>(B, RO, rec1, L, RIGHT, valid);
-        load_evol_sys<N>(C, 0, rec + GE::OREC, L, LEFT, CUR, valid && j >= 1);
+        load_obs_sys<N>(B, OB, rec1, L, RIGHT, valid);
+        load_evol_sys<N>(C, EC, rec + GE::OREC, L, LEFT, CUR, valid && j >= 1);
     }
 
     // step 1 (pivots on cur lanes)
-    hqr<HA, N>(A, gl, gb, 0);
+    hqr<HA, N, T, TO>(A, gl, gb, 0);
 #pragma unroll
-    for (int r = 0; r < RO; ++r) B[r] = A[N + r];
+    for (int r = 0; r < RO; ++r) B[DB + r] = A[N + r];
 #pragma unroll
-    for (int r = 0; r < N; ++r) C[N + r] = A[r];
+    for (int r = 0; r < N; ++r) C[RC + r] = A[r];
 
     // step 3 (pivots on right lanes) and step 2 (pivots on cur lanes)
-    hqr<HB, N>(B, gl, gb, N);
-    hqr<HC, N>(C, gl, gb, 0);
+    hqr<HB, N, T, TO>(B, gl, gb, N);
+    hqr<HC, N, T, TC>(C, gl, gb, 0);
 
     store_rrow<N>(slot<T>(a.rrows, t, GE::RREC), C, gl, valid);
     diag_stats<N>(C, L, valid, dmin, dmax, nonfinite);
@@ -552,7 +576,7 @@ __device__ __forceinline__ void base_unit(const FwdArgs &a, bool valid, int gl, 
     } else {
         load_obs_sys<N>(A, 0, slot<TIN>(a.sys_in, 0, Geo<N>::SREC), L, CUR, valid);
     }
-    hqr<RO, N>(A, gl, gb, 0);
+    if constexpr (RAW) hqr<RO, N>(A, gl, gb, 0);  // a reduced observation block is already triangular
     double R[N];
 #pragma unroll
     for (int r = 0; r < N; ++r) R[r] = (r < RO && (L.role == CUR || L.role == RHS)) ? A[r] : 0.0;
@@ -589,7 +613,8 @@ __device__ __forceinline__ void rank_flag(double dmin, double dmax, double tol, 
 // With FOLD, the last unit of an odd level also folds the last column in
 // (its statistics join its block's slot; the level's fold slot is set neutral).
 template <int N, int MM, bool RAW, class T, class TIN, bool BATCH, bool FOLD = false>
-__global__ __launch_bounds__(kBlock) void k_forward(FwdArgs a0, const FwdArgs *tab, BlockMap bm) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(wf_min_waves(N)))) void k_forward(
+    FwdArgs a0, const FwdArgs *tab, BlockMap bm) {
     const FwdArgs &a = BATCH ? tab[bm.item[blockIdx.x]] : a0;
     const int64_t blk = BATCH ? bm.blk[blockIdx.x] : (int64_t)blockIdx.x;
     const Grp<N> g;
