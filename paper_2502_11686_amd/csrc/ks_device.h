@@ -293,6 +293,7 @@ __device__ __forceinline__ void load_obs_raw(T (&x)[H], int roff, T (&cv)[MM],
     const int m = a.m;
     const int col = (L.role == own) ? L.rc : (L.role == rhs ? N : -1);
     const bool ld = valid && col >= 0;
+    j -= a.col0;
     const double *Gj = a.G + j * (int64_t)m * N;
     const double *oj = a.o + j * (int64_t)m;
 #pragma unroll
@@ -318,7 +319,7 @@ template <int N, int H, class LR, class T>
 __device__ __forceinline__ void load_evol_raw(T (&x)[H], int roff, T (&cv)[N], int64_t i,
                                               const LR &L, int gl, int role_m,
                                               int role_p, int cl0, const FwdArgs &a, bool valid) {
-    const int64_t t = i - 1;  // ABI entry of step i
+    const int64_t t = i - 1 - a.ent0;  // ABI entry of step i (relative to the first one the pointers hold)
     const double *F = a.F + t * N * N;
     const double *Hm = a.H ? a.H + t * N * N : nullptr;
     const double *c = a.c + t * N;
@@ -423,8 +424,10 @@ __device__ __forceinline__ const T *slot(const double *base, int64_t idx, int st
 // The last column jl = N_l - 1 of a level with N_l odd (even, no right
 // neighbour): its R row (record t+1), and its Z rows, which touch only column
 // jl - 1, stacked under the step-3 triangle Onew of the last unit t.
+// Inputs are read through `in` (the level's arguments, or a view of them in
+// LDS), results written through `a`.
 template <int N, int MM, bool RAW, class T, class TIN>
-__device__ __forceinline__ void fold_part(const FwdArgs &a, int64_t t, int gl, int gb,
+__device__ __forceinline__ void fold_part(const FwdArgs &a, const FwdArgs &in, int64_t t, int gl, int gb,
                                           const LaneRole<N> &L, T (&Onew)[N], double &dmin,
                                           double &dmax, bool &bad, bool &nonfinite) {
     using GE = Geo<N>;
@@ -436,14 +439,14 @@ __device__ __forceinline__ void fold_part(const FwdArgs &a, int64_t t, int gl, i
     T A2[RO], C2[HC];
     if constexpr (RAW) {
         T cvO[MM], cvE[N];
-        load_obs_raw<N, MM>(A2, 0, cvO, jl, L, gl, CUR, 0, a, true);
-        load_evol_raw<N>(C2, N, cvE, jl, L, gl, LEFT, CUR, 2 * N + 1, a, true);
+        load_obs_raw<N, MM>(A2, 0, cvO, jl, L, gl, CUR, 0, in, true);
+        load_evol_raw<N>(C2, N, cvE, jl, L, gl, LEFT, CUR, 2 * N + 1, in, true);
         whiten<RO, MM>(a.C_diag, A2, 0, cvO, gl, gb, 0, bad);
         whiten<HC, N>(a.K_diag, C2, N, cvE, gl, gb, 2 * N + 1, bad);
         hqr<RO, N>(A2, gl, gb, 0);
     } else {
         // a reduced observation block is already triangular
-        const TIN *rec = slot<TIN>(a.sys_in, jl, GE::SREC);
+        const TIN *rec = slot<TIN>(in.sys_in, jl - in.col0, GE::SREC);
         load_obs_sys<N>(A2, 0, rec, L, CUR, true);
         load_evol_sys<N>(C2, N, rec + GE::OREC, L, LEFT, CUR, true);
     }
@@ -470,8 +473,8 @@ __device__ __forceinline__ void fold_part(const FwdArgs &a, int64_t t, int gl, i
 // (plus, with INLINE_FOLD, the last column when it is the folding unit; the
 // per-level kernels leave that to k_fold).  No workgroup barrier.
 template <int N, int MM, bool RAW, bool INLINE_FOLD, class T, class TIN>
-__device__ __forceinline__ void fwd_unit(const FwdArgs &a, int64_t t, bool in, int gl, int gb,
-                                         double &dmin, double &dmax, bool &bad, bool &nonfinite,
+__device__ __forceinline__ void fwd_unit(const FwdArgs &a, const FwdArgs &src, int64_t t, bool in, int gl,
+                                         int gb, double &dmin, double &dmax, bool &bad, bool &nonfinite,
                                          int64_t t_end = -1) {
     using GE = Geo<N>;
     constexpr int RO = RAW ? MM : N;            // rows of an observation block
@@ -503,18 +506,18 @@ __device__ __forceinline__ void fwd_unit(const FwdArgs &a, int64_t t, bool in, i
 #pragma unroll
         for (int r = N; r < HC; ++r) C[r] = T(0);
         T cvOa[MM], cvOb[MM], cvEa[N], cvEc[N];
-        load_obs_raw<N, MM>(A, 0, cvOa, j, L, gl, CUR, 0, a, valid);
-        load_evol_raw<N>(A, RO, cvEa, j + 1, L, gl, CUR, RIGHT, 0, a, valid);
-        load_obs_raw<N, MM>(B, OB, cvOb, j + 1, L, gl, RIGHT, N, a, valid);
-        load_evol_raw<N>(C, EC, cvEc, j, L, gl, LEFT, CUR, 2 * N + 1, a, valid && j >= 1);
+        load_obs_raw<N, MM>(A, 0, cvOa, j, L, gl, CUR, 0, src, valid);
+        load_evol_raw<N>(A, RO, cvEa, j + 1, L, gl, CUR, RIGHT, 0, src, valid);
+        load_obs_raw<N, MM>(B, OB, cvOb, j + 1, L, gl, RIGHT, N, src, valid);
+        load_evol_raw<N>(C, EC, cvEc, j, L, gl, LEFT, CUR, 2 * N + 1, src, valid && j >= 1);
         whiten<HA, MM>(a.C_diag, A, 0, cvOa, gl, gb, 0, bad);
         whiten<HA, N>(a.K_diag, A, RO, cvEa, gl, gb, 0, bad);
         whiten<HB, MM>(a.C_diag, B, OB, cvOb, gl, gb, N, bad);
         whiten<HC, N>(a.K_diag, C, EC, cvEc, gl, gb, 2 * N + 1, bad);
     } else {
-        const TIN *rec = slot<TIN>(a.sys_in, j, GE::SREC);
+        const TIN *rec = slot<TIN>(src.sys_in, j - src.col0, GE::SREC);
         load_obs_sys<N>(A, 0, rec, L, CUR, valid);
-        const TIN *rec1 = slot<TIN>(a.sys_in, j + 1, GE::SREC);
+        const TIN *rec1 = slot<TIN>(src.sys_in, j + 1 - src.col0, GE::SREC);
         load_evol_sys<N>(A, RO, rec1 + GE::OREC, L, CUR, RIGHT, valid);
         load_obs_sys<N>(B, OB, rec1, L, RIGHT, valid);
         load_evol_sys<N>(C, EC, rec + GE::OREC, L, LEFT, CUR, valid && j >= 1);
@@ -548,7 +551,7 @@ __device__ __forceinline__ void fwd_unit(const FwdArgs &a, int64_t t, bool in, i
 #pragma unroll
     for (int r = 0; r < N; ++r) Onew[r] = r < PB ? B[r] : T(0);
 
-    if (INLINE_FOLD && fold) fold_part<N, MM, RAW, T, TIN>(a, t, gl, gb, L, Onew, dmin, dmax, bad, nonfinite);
+    if (INLINE_FOLD && fold) fold_part<N, MM, RAW, T, TIN>(a, src, t, gl, gb, L, Onew, dmin, dmax, bad, nonfinite);
 
     // reduced column t, observation block from step 3 (with the fold, if any)
     if (valid) {
@@ -609,6 +612,78 @@ __device__ __forceinline__ void rank_flag(double dmin, double dmax, double tol, 
         atomicOr(flags, FLAG_RANK);
 }
 
+// Staging of a workgroup's inputs in LDS.  The workgroup's units read
+// columns [J0, J0 + NC) of the level (NC = 2 UPB + 1: two per unit and the
+// fold column): consecutive threads copy consecutive words of those columns'
+// records (reduced systems) or of their slices of the raw per-step arrays
+// (level 0), so every global load is a full, coalesced line; each lane then
+// reads its own column's entries from LDS.  Used at level 0 where the copy
+// fits in 40 KB (several workgroups per CU): there a unit's inputs are six
+// arrays' scattered slices (n = 6: level-0 forward 123 -> 110 us).  Above it
+// a unit reads two whole records and the per-lane loads are already close to
+// coalesced; the barrier the copy adds made those levels slower.
+template <int N, int MM, bool RAW>
+struct Stage {
+    static constexpr int NC = 2 * Geo<N>::UPB + 1;
+    // words per column: raw G, o, C (dense), F, H, c, K (dense); or one record
+    static constexpr int PER = RAW ? MM * N + MM + MM * MM + 2 * N * N + N + N * N : Geo<N>::SREC;
+    static constexpr int WORDS = NC * PER;
+    static constexpr bool ON = RAW && WORDS * 8 <= 40 * 1024;
+};
+
+__device__ __forceinline__ void stage_copy(double *dst, const double *src, int64_t count) {
+    for (int64_t e = threadIdx.x; e < count; e += kBlock) dst[e] = src[e];
+}
+
+// Copies what the workgroup's units read into lds and points `v` (a copy of
+// the level's arguments) at it, indexed as the originals.  Ends with a
+// workgroup barrier.
+template <int N, int MM, bool RAW, class TIN>
+__device__ __forceinline__ void stage_inputs(const FwdArgs &a, int64_t blk, double *lds, FwdArgs &v) {
+    using SG = Stage<N, MM, RAW>;
+    const int64_t J0 = 2 * blk * Geo<N>::UPB;
+    const int64_t nc = a.Nl - J0 < SG::NC ? a.Nl - J0 : SG::NC;  // columns that exist
+    if constexpr (RAW) {
+        const int64_t m = a.m;
+        const int64_t cm = a.C_diag ? m : m * m, kk = a.K_diag ? N : N * N;
+        // observation steps J0 .. J0+nc-1; evolution entries J0-1 .. J0+nc-2 (>= 0)
+        const int64_t e0 = J0 > 0 ? J0 - 1 : 0, ne = J0 + nc - 1 - e0;
+        // every view points at the start of its section; loads index relative
+        // to col0 (observation steps) and ent0 (evolution entries)
+        double *p = lds;
+        auto put = [&](const double *src, int64_t first, int64_t count, int64_t w, const double *&view) {
+            stage_copy(p, src + first * w, count * w);
+            view = p;
+            p += SG::NC * w;
+        };
+        put(a.G, J0, nc, m * N, v.G);
+        put(a.o, J0, nc, m, v.o);
+        put(a.C, J0, nc, cm, v.C);
+        put(a.F, e0, ne, N * N, v.F);
+        put(a.c, e0, ne, N, v.c);
+        put(a.K, e0, ne, kk, v.K);
+        if (a.H) put(a.H, e0, ne, N * N, v.H);
+        v.col0 = J0;
+        v.ent0 = e0;
+    } else {
+        constexpr int SR = Geo<N>::SREC;
+        if constexpr (sizeof(TIN) == 4) {
+            // FP32 records fill the first half of their slot (SR floats, rounded up to whole words)
+            constexpr int HW = (SR + 1) / 2;
+            const double *src = a.sys_in + J0 * SR;
+            for (int64_t e = threadIdx.x; e < nc * HW; e += kBlock) {
+                const int64_t col = e / HW, off = e - col * HW;
+                lds[col * SR + off] = src[col * SR + off];
+            }
+        } else {
+            stage_copy(lds, a.sys_in + J0 * SR, nc * SR);
+        }
+        v.sys_in = lds;
+        v.col0 = J0;
+    }
+    __syncthreads();
+}
+
 // one forward level, one unit per G lanes, many workgroups
 // With FOLD, the last unit of an odd level also folds the last column in
 // (its statistics join its block's slot; the level's fold slot is set neutral).
@@ -621,7 +696,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(wf_min_w
     bool bad = false, nonfinite = false;
     double dmin = INFINITY, dmax = 0.0;
     const int64_t t = blk * Geo<N>::UPB + g.ui;
-    fwd_unit<N, MM, RAW, FOLD, T, TIN>(a, t, g.in, g.gl, g.gbase, dmin, dmax, bad, nonfinite);
+    if constexpr (Stage<N, MM, RAW>::ON) {
+        __shared__ double lds[Stage<N, MM, RAW>::WORDS];
+        FwdArgs v = a;
+        stage_inputs<N, MM, RAW, TIN>(a, blk, lds, v);
+        fwd_unit<N, MM, RAW, FOLD, T, TIN>(a, v, t, g.in, g.gl, g.gbase, dmin, dmax, bad, nonfinite);
+    } else {
+        fwd_unit<N, MM, RAW, FOLD, T, TIN>(a, a, t, g.in, g.gl, g.gbase, dmin, dmax, bad, nonfinite);
+    }
     block_minmax<kBlock>(dmin, dmax, bad, nonfinite, a.flags);
     if (threadIdx.x == 0) {
         a.slots[2 * blk] = dmin;
@@ -649,7 +731,7 @@ __global__ __launch_bounds__(kBlock) void k_fold(FwdArgs a0, const FwdArgs *tab,
     if (g.ui == 0) {  // one unit: lanes of the other units stay idle
         T Onew[N];
         load_obs_sys<N>(Onew, 0, slot<T>(a.sys_out, t, GE::SREC), L, RIGHT, valid);
-        fold_part<N, MM, RAW, T, TIN>(a, t, g.gl, g.gbase, L, Onew, dmin, dmax, bad, nonfinite);
+        fold_part<N, MM, RAW, T, TIN>(a, a, t, g.gl, g.gbase, L, Onew, dmin, dmax, bad, nonfinite);
         if (valid) {
             const int oc = L.role == RIGHT ? L.rc : (L.role == RHS ? N : -1);
             if (oc >= 0) {
@@ -696,9 +778,9 @@ __global__ __launch_bounds__(kTailBlock) void k_fwd_tail(FwdTailArgs ta0, const 
         } else {
             for (int64_t t0 = 0; t0 < a.units; t0 += UPB) {
                 if (RAW0 && l == 0)
-                    fwd_unit<N, MM, true, true, double, double>(a, t0 + g.ui, g.in, g.gl, g.gbase, dmin, dmax, bad, nonfinite);
+                    fwd_unit<N, MM, true, true, double, double>(a, a, t0 + g.ui, g.in, g.gl, g.gbase, dmin, dmax, bad, nonfinite);
                 else
-                    fwd_unit<N, MM, false, true, double, double>(a, t0 + g.ui, g.in, g.gl, g.gbase, dmin, dmax, bad, nonfinite);
+                    fwd_unit<N, MM, false, true, double, double>(a, a, t0 + g.ui, g.in, g.gl, g.gbase, dmin, dmax, bad, nonfinite);
             }
         }
         __syncthreads();  // the next level reads what this workgroup wrote: workgroup scope suffices
@@ -739,10 +821,10 @@ __global__ __launch_bounds__(kBlock) void k_fwd_multi(FwdMultiArgs ma) {
         const int64_t hi = (w == ma.groups - 1) ? a.units : lo + span;
         for (int64_t t0 = lo; t0 < hi; t0 += GE::UPB) {
             if (x == 0) {
-                fwd_unit<N, MM, RAW0, true, T, TIN>(a, t0 + g.ui, g.in, g.gl, g.gbase, dmin, dmax, bad,
+                fwd_unit<N, MM, RAW0, true, T, TIN>(a, a, t0 + g.ui, g.in, g.gl, g.gbase, dmin, dmax, bad,
                                                     nonfinite, hi);
             } else {
-                fwd_unit<N, MM, false, true, T, T>(a, t0 + g.ui, g.in, g.gl, g.gbase, dmin, dmax, bad,
+                fwd_unit<N, MM, false, true, T, T>(a, a, t0 + g.ui, g.in, g.gl, g.gbase, dmin, dmax, bad,
                                                    nonfinite, hi);
             }
         }

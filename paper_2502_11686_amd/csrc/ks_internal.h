@@ -38,6 +38,10 @@ struct FwdArgs {
     double *slots;    // per-block [min |R_pp|, max |R_pp|]
     double *fold_slot;  // [min, max] of the level's fold kernel
     unsigned *flags;
+    // first column (observation step, reduced-system record) and first
+    // evolution entry that the input pointers above start at: 0 for the
+    // caller's arrays; nonzero when a kernel reads a staged copy of a slice
+    int64_t col0, ent0;
 };
 
 // Forward levels l0..L in one workgroup, then the rank test.
