@@ -48,6 +48,23 @@ struct BSmem {
     static constexpr int PER = DO + 3 * N;           // 1 / R_ii(r, r), y_a, y_b
 };
 
+// Synchronization inside one record's work.  A record taken by one
+// wavefront (n <= 12) shares its LDS region with no other wavefront, and a
+// wavefront's LDS accesses complete in order: fences that keep the compiler
+// from reordering around a wavefront barrier suffice, and the other records
+// of the workgroup run on without waiting.  Larger records span several
+// wavefronts and use the workgroup barrier.
+template <int WPU>
+__device__ __forceinline__ void rec_sync() {
+    if constexpr (WPU == 1) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 // One block row (record t of level l): back-substitution and Algorithm 2.
 //  1. T = R_ii^{-1} [R_i,b | rho_i | R_i,a] and RI = R_ii^{-1}: one right-hand
 //     side column per thread, column-oriented substitution (independent
@@ -136,9 +153,9 @@ __device__ __forceinline__ void blk_bwd_unit(const BwdArgs &a, int l, int64_t t,
         DI[N + g] = ya;
         DI[2 * N + g] = yb;
     }
-    __syncthreads();
+    rec_sync<WPU>();
     if (g < N) DI[g] = rcp_nr(Rd[g * LR + g]);
-    __syncthreads();
+    rec_sync<WPU>();
     if (g < W && (DO_COV || g >= N)) {
         double x[N];
 #pragma unroll
@@ -172,7 +189,7 @@ __device__ __forceinline__ void blk_bwd_unit(const BwdArgs &a, int l, int64_t t,
             }
         }
     }
-    __syncthreads();
+    rec_sync<WPU>();
     // T_I(r, d): d < n the a-part (T_a), d >= n the b-part (T_b)
     auto TI = [&](int r, int d) -> double {
         return d < N ? TT[r * LT + N + 1 + d] : TT[r * LT + (d - N)];
@@ -227,7 +244,7 @@ __device__ __forceinline__ void blk_bwd_unit(const BwdArgs &a, int l, int64_t t,
                 }
             }
         }
-        __syncthreads();  // R_ii no longer read: region 0 takes P
+        rec_sync<WPU>();  // R_ii no longer read: region 0 takes P
         double *PP = Rd;
 #pragma unroll
         for (int u = 0; u < QP; ++u) {
@@ -254,7 +271,7 @@ __device__ __forceinline__ void blk_bwd_unit(const BwdArgs &a, int l, int64_t t,
                 }
             }
         }
-        __syncthreads();
+        rec_sync<WPU>();
         // S_ii = RI RI^T + P T_I^T: A = [RI | P] (n x 3n), B(k, c) = [RI | T_I](c, k)
         mf_d4 sc[QS];
 #pragma unroll
@@ -276,7 +293,7 @@ __device__ __forceinline__ void blk_bwd_unit(const BwdArgs &a, int l, int64_t t,
                 }
             }
         }
-        __syncthreads();  // P no longer read: region 0 takes S_ii
+        rec_sync<WPU>();  // P no longer read: region 0 takes S_ii
         double *SS = Rd;
 #pragma unroll
         for (int u = 0; u < QS; ++u) {
@@ -291,7 +308,7 @@ __device__ __forceinline__ void blk_bwd_unit(const BwdArgs &a, int l, int64_t t,
                 }
             }
         }
-        __syncthreads();
+        rec_sync<WPU>();
         if (valid) {
             for (int idx = g; idx < N * N; idx += NT) {
                 const int r = idx / N, c = idx - r * N;
@@ -299,7 +316,7 @@ __device__ __forceinline__ void blk_bwd_unit(const BwdArgs &a, int l, int64_t t,
             }
         }
     }
-    __syncthreads();
+    rec_sync<WPU>();
 }
 
 template <int N, bool DO_Y, bool DO_COV, class TR, bool BATCH>
@@ -353,6 +370,7 @@ __global__ __launch_bounds__(BGeo<N>::TBB) void k_blk_bwd_multi(BwdArgs a) {
         const int64_t hi = lo + span < recs ? lo + span : recs;
         for (int64_t t0 = lo; t0 < hi; t0 += BG::RPW)
             blk_bwd_unit<N, DO_Y, DO_COV, TR>(a, l, t0 + u, hi, a.store_s && l >= 1, sm + u * PER);
+        __syncthreads();  // the next level reads what this workgroup's records wrote
     }
 }
 
