@@ -227,10 +227,13 @@ ks_status ks_kernel_time(const ks_plan *plan, double *total_ms, int64_t *count);
 /* ---------------------------------------------------------------- tuning
  *
  * The schedule's free choices, per state dimension n (1..64) and precision
- * form.  None of them changes what is computed: every unit and block row
- * does the same arithmetic whichever launch runs it, so FP64 results are
- * bitwise independent of them (the FP32 switch changes which levels run in
- * FP32, hence FP32-form results).
+ * form.  None of them changes what is computed: with the same kernel
+ * variants every unit and block row does the same arithmetic whichever
+ * launch runs it, so FP64 results are bitwise independent of the tail passes
+ * and level groups (the FP32 switch changes which levels run in FP32, hence
+ * FP32-form results; another kernel variant is another compiled kernel and
+ * may round differently).  Plans, batches and the engine read the same
+ * table, so a problem's results are the same through all three.
  *   fwd_tail_passes, bwd_tail_passes: the top levels that need at most that
  *     many passes of the single-workgroup forward (backward) tail kernel run
  *     inside it instead of one launch each (0: the base level only);
@@ -242,14 +245,17 @@ ks_status ks_kernel_time(const ks_plan *plan, double *total_ms, int64_t *count);
  *     wrote one level down, so levels are separated by workgroup barriers);
  *     1 = one launch per level;
  *   bwd_group, bwd_group_from: the same for the backward levels below the
- *     backward tail (groups bwd_group_from + q bwd_group .. + bwd_group - 1).
+ *     backward tail (groups bwd_group_from + q bwd_group .. + bwd_group - 1);
+ *   fwd_variant, bwd_variant: which compiled shape variant of the forward and
+ *     backward kernels runs (ks_kernel_variants), for plans, batches and the
+ *     engine alike; a variant that does not exist means the default.
  * Groups apply to single plans (ks_smooth*, ks_covariances,
  * ks_smooth_cov_static) where the kernel family has group kernels, never
  * cross the FP32 switch and stay below the tails.  Defaults 2, 2, 1024,
- * 1, 1, 1, 1; an autotuned table is applied by the Python binding; the
+ * 1, 1, 1, 1, 0, 0; an autotuned table is applied by the Python binding; the
  * environment variables KS_TAIL_PASSES (both pass counts), KS_FP32_SWITCH,
- * KS_FWD_GROUP, KS_FWD_GROUP_FROM, KS_BWD_GROUP and KS_BWD_GROUP_FROM
- * override every entry.  Plans, batches and engine requests read the table
+ * KS_FWD_GROUP, KS_FWD_GROUP_FROM, KS_BWD_GROUP, KS_BWD_GROUP_FROM,
+ * KS_FWD_VARIANT and KS_BWD_VARIANT override every entry.  Plans, batches and engine requests read the table
  * when they are created; not safe to call concurrently with those. */
 typedef struct {
     int32_t fwd_tail_passes;
@@ -259,11 +265,23 @@ typedef struct {
     int32_t fwd_group_from;        /* >= 0 */
     int32_t bwd_group;             /* 1..8 */
     int32_t bwd_group_from;        /* >= 0 */
+    int32_t fwd_variant;           /* compiled forward variant (0 = default) */
+    int32_t bwd_variant;           /* compiled backward variant (0 = default) */
 } ks_tuning;
 
 ks_status ks_set_tuning(int32_t n, int32_t precision, const ks_tuning *t);
 /* effective values (environment overrides applied) */
 ks_status ks_get_tuning(int32_t n, int32_t precision, ks_tuning *out);
+/* Number of compiled forward (backward = 0) or backward (backward != 0)
+ * variants for state dimension n and observation dimension m, 0 when (n, m)
+ * is unsupported.  Variants differ in launch shape only, not in what is
+ * computed: forward variant 1 runs level 0 without staging a workgroup's
+ * inputs in LDS; backward variants of the MFMA family take 4, 2 or 1 records
+ * per workgroup (n <= 12; n = 16, 24: 2 or 1; n = 32: 1 or 2), and for
+ * n = 1, 2, 3, 5 backward variant 1 is the MFMA family instead of the
+ * wavefront family (then results differ from variant 0 by rounding only).
+ * Host-only. */
+int32_t ks_kernel_variants(int32_t n, int32_t m, int32_t backward);
 /* the plan's schedule: number of FP32 levels, first level of the forward tail
  * launch, lowest level of the backward tail launch (states + covariances) */
 ks_status ks_plan_schedule(const ks_plan *plan, int32_t *fp32_levels, int32_t *fwd_tail_level,

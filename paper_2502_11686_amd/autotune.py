@@ -1,20 +1,31 @@
-"""Autotuner of the schedule's free choices, per state dimension and form.
+"""Autotuner of the kernels' shape variants and the schedule's free choices,
+per state dimension and precision form.
 
-For each (n, form) it smooths one synthetic problem of that n (long enough
-that the top levels of any longer problem look the same: their unit counts
-do not depend on k) with every candidate setting and keeps the fastest:
+For each (n, form) it smooths one synthetic problem of that n and times the
+candidates of each choice in turn, keeping the best so far for the next:
 
-* forward tail passes: how many unit passes of the single-workgroup forward
-  tail kernel the top levels may take instead of one launch each (timed over
-  the forward launches, KS_TIME_FWD_ALL);
-* backward tail passes: the same for the backward tail (KS_TIME_BWD_ALL);
-* FP32 form: the column count above which a level runs in FP32 (timed over
-  whole passes).
+* backward variant: the compiled shapes of the backward kernels (records per
+  MFMA workgroup; for n = 1, 2, 3, 5 the MFMA family instead of the wavefront
+  family), timed over the backward launches (KS_TIME_BWD_ALL);
+* forward variant: level 0 with or without its inputs staged in LDS, timed
+  over the forward launches (KS_TIME_FWD_ALL);
+* forward and backward tail passes: how many unit passes of the
+  single-workgroup tail kernels the top levels may take instead of one launch
+  each;
+* level groups: several consecutive levels per launch from a given level on
+  (forward: where the kernel family has group kernels; backward);
+* FP32 form: the column count above which a level runs in FP32.  A width is
+  admissible only if the FP32-form errors against the FP64 path of the same
+  problem stay within 1e-5 (states normwise, covariance blocks per block).
 
-The choice depends only on (n, form), never on what a batch holds, and none
-of the choices changes an FP64 result (tail and per-level kernels do the same
-arithmetic).  The table is JSON; ks.load_tuning applies it, and the binding
-loads tune_mi355x.json next to the library by default.
+A candidate replaces the current choice only if its median beats the current
+median by more than 2 % and by more than the spread (median absolute
+deviation) of the current choice's repeats, so timing noise never moves a
+choice.  Variants and schedule choices change launch shapes, not what is
+computed (apart from the FP32 switch, and the wavefront / MFMA choice at
+n <= 5, which change rounding); the choice depends only on (n, form), never
+on what a batch holds.  The table is JSON; ks.load_tuning applies it, and the
+binding loads tune_mi355x.json next to the library by default.
 
     python -m paper_2502_11686_amd.autotune [--out FILE] [--n 6 12 ...] [--reps R]
 """
@@ -33,79 +44,129 @@ from . import gen, ks
 
 PASSES = (0, 1, 2, 3, 4, 6, 8, 12)
 SWITCHES = (256, 512, 1024, 2048, 4096)
+GROUP_SIZES = (2, 3, 4)
+GROUP_FROM = (1, 3, 5, 7, 9, 11)
 ALL_N = (1, 2, 3, 4, 5, 6, 8, 12, 16, 24, 32, 48)
+FP32_GATE = 1e-5
+
+
+def problem_k(n: int) -> int:
+    """Trajectory length the table is tuned at: the single-problem workloads'
+    lengths for small n (their top levels are what the tail and group choices
+    act on), shorter where a pass is long."""
+    return 100000 if n <= 8 else (50000 if n <= 12 else (20000 if n <= 16 else 4096))
 
 
 def _problem(n: int):
-    k = 32768 if n <= 8 else (16384 if n <= 16 else 4096)
-    return gen.make_problem(np.random.default_rng(7000 + n), k, n, max(1, n // 2), F_mode="per_step", cov="diag")
+    return gen.make_problem(np.random.default_rng(7000 + n), problem_k(n), n, max(1, n // 2),
+                            F_mode="per_step", cov="diag")
 
 
-def _timed(p, args, fp32: bool, kind: int, reps: int) -> float:
+def _mad(xs):
+    m = statistics.median(xs)
+    return statistics.median([abs(x - m) for x in xs])
+
+
+def _timed(p, args, fp32: bool, kind, reps: int):
+    """Repeats of one timing: milliseconds of the selected launches per call
+    (kind) or of whole calls (kind None); and the outputs."""
     plan = ks.Plan(p.k, p.n, p.m, p.K_diag, p.C_diag, fp32=fp32)
     try:
         u = torch.empty((p.k + 1, p.n), dtype=torch.float64, device="cuda")
         S = torch.empty((p.k + 1, p.n, p.n), dtype=torch.float64, device="cuda")
-        plan.smooth_cov(*args, u_out=u, cov_out=S)  # warm-up
+        plan.smooth_cov(*args, u_out=u, cov_out=S)  # warm-up (and graph capture)
+        plan.smooth_cov(*args, u_out=u, cov_out=S)
+        out = []
         if kind is None:
             torch.cuda.synchronize()
-            ts = []
             for _ in range(reps):
                 t0 = time.perf_counter()
                 plan.smooth_cov(*args, u_out=u, cov_out=S)
-                ts.append(time.perf_counter() - t0)
-            return statistics.median(ts) * 1e3
-        plan.time_kernels(kind)
-        ms = []
-        for _ in range(reps):
-            plan.time_kernels(kind)
-            plan.smooth_cov(*args, u_out=u, cov_out=S)
-            t, cnt = plan.kernel_time()
-            ms.append(t / max(cnt, 1))
-        plan.time_kernels(ks.KS_TIME_OFF)
-        return statistics.median(ms)
+                out.append((time.perf_counter() - t0) * 1e3)
+        else:
+            for _ in range(reps):
+                plan.time_kernels(kind)
+                plan.smooth_cov(*args, u_out=u, cov_out=S)
+                t, cnt = plan.kernel_time()
+                out.append(t / max(cnt, 1))
+            plan.time_kernels(ks.KS_TIME_OFF)
+        return out, u, S
     finally:
         plan.close()
 
 
-def tune_one(n: int, fp32: bool, reps: int = 7) -> dict:
+def _choose(n, fp32, keys, candidates, p, args, kind, reps, cur, log, admissible=None):
+    """Time every candidate value of the tuning keys and move the current
+    choice to the fastest by the noise rule; returns the new choice and the
+    median milliseconds per candidate."""
+    times = {}
+    for c in candidates:
+        ks.set_tuning(n, fp32, **dict(cur, **dict(zip(keys, c))))
+        ts, u, S = _timed(p, args, fp32, kind, reps)
+        if admissible is not None and not admissible(u, S):
+            print(f"  n={n} {keys}={c}: outside the FP32-form gate, not admissible", file=log, flush=True)
+            continue
+        times[c] = (statistics.median(ts), _mad(ts))
+    base = tuple(cur[k] for k in keys)
+    if base not in times:  # the current choice itself, timed the same way
+        ks.set_tuning(n, fp32, **cur)
+        ts, _u, _S = _timed(p, args, fp32, kind, reps)
+        times[base] = (statistics.median(ts), _mad(ts))
+    best = min(times, key=lambda c: times[c][0])
+    m0, d0 = times[base]
+    if best != base and times[best][0] < m0 * 0.98 and m0 - times[best][0] > d0:
+        cur = dict(cur, **dict(zip(keys, best)))
+    ks.set_tuning(n, fp32, **cur)
+    return cur, {"/".join(map(str, c)): round(v[0], 4) for c, v in times.items()}
+
+
+def tune_one(n: int, fp32: bool, reps: int = 7, log=sys.stderr) -> dict:
     p = _problem(n)
     args = ks.to_device(p)
-    base = ks.get_tuning(n, fp32)
-    sw = base["fp32_switch_columns"]
-    fwd = {}
-    for q in PASSES:
-        ks.set_tuning(n, fp32, fwd_tail_passes=q, bwd_tail_passes=base["bwd_tail_passes"], fp32_switch_columns=sw)
-        fwd[q] = _timed(p, args, fp32, ks.KS_TIME_FWD_ALL, reps)
-    best_f = min(fwd, key=fwd.get)
-    bwd = {}
-    for q in PASSES:
-        ks.set_tuning(n, fp32, fwd_tail_passes=best_f, bwd_tail_passes=q, fp32_switch_columns=sw)
-        bwd[q] = _timed(p, args, fp32, ks.KS_TIME_BWD_ALL, reps)
-    best_b = min(bwd, key=bwd.get)
-    best_s, sws = sw, {}
+    cur = dict(ks.TUNING_DEFAULTS)
+    ks.set_tuning(n, fp32, **cur)
+    rec = {}
+    nbv = ks.kernel_variants(n, p.m, True)
+    nfv = ks.kernel_variants(n, p.m, False)
+    cur, rec["bwd_variant_ms"] = _choose(n, fp32, ("bwd_variant",), [(v,) for v in range(nbv)], p, args,
+                                         ks.KS_TIME_BWD_ALL, reps, cur, log)
+    cur, rec["fwd_variant_ms"] = _choose(n, fp32, ("fwd_variant",), [(v,) for v in range(nfv)], p, args,
+                                         ks.KS_TIME_FWD_ALL, reps, cur, log)
+    cur, rec["fwd_ms"] = _choose(n, fp32, ("fwd_tail_passes",), [(q,) for q in PASSES], p, args,
+                                 ks.KS_TIME_FWD_ALL, reps, cur, log)
+    cur, rec["bwd_ms"] = _choose(n, fp32, ("bwd_tail_passes",), [(q,) for q in PASSES], p, args,
+                                 ks.KS_TIME_BWD_ALL, reps, cur, log)
+    groups = [(g, f) for g in GROUP_SIZES for f in GROUP_FROM]
+    if n <= 12:  # forward group kernels exist for the wavefront family
+        cur, rec["fwd_group_ms"] = _choose(n, fp32, ("fwd_group", "fwd_group_from"), groups, p, args,
+                                           ks.KS_TIME_FWD_ALL, reps, cur, log)
+    cur, rec["bwd_group_ms"] = _choose(n, fp32, ("bwd_group", "bwd_group_from"), groups, p, args,
+                                       ks.KS_TIME_BWD_ALL, reps, cur, log)
     if fp32:
-        for s in SWITCHES:
-            ks.set_tuning(n, fp32, fwd_tail_passes=best_f, bwd_tail_passes=best_b, fp32_switch_columns=s)
-            sws[s] = _timed(p, args, fp32, None, reps)
-        best_s = min(sws, key=sws.get)
-    ks.set_tuning(n, fp32, fwd_tail_passes=best_f, bwd_tail_passes=best_b, fp32_switch_columns=best_s)
-    return dict(n=n, form="fp32" if fp32 else "fp64", fwd_tail_passes=best_f, bwd_tail_passes=best_b,
-                fp32_switch_columns=best_s, k=p.k,
-                fwd_ms={str(q): round(v, 4) for q, v in fwd.items()},
-                bwd_ms={str(q): round(v, 4) for q, v in bwd.items()},
-                pass_ms_by_switch={str(q): round(v, 4) for q, v in sws.items()})
+        saved64 = ks.get_tuning(n, False)
+        ks.set_tuning(n, False, **ks.TUNING_DEFAULTS)
+        _ts, u64, S64 = _timed(p, args, False, None, 1)
+        ks.set_tuning(n, False, **saved64)
+        s_norm = torch.linalg.matrix_norm(S64)
+        u_max = u64.abs().max()
+
+        def admissible(u, S):
+            eu = float((u - u64).abs().max() / u_max)
+            es = float((torch.linalg.matrix_norm(S - S64) / s_norm).max())
+            return eu <= FP32_GATE and es <= FP32_GATE
+
+        cur, rec["pass_ms_by_switch"] = _choose(n, fp32, ("fp32_switch_columns",), [(s,) for s in SWITCHES], p,
+                                                args, None, reps, cur, log, admissible)
+    ks.set_tuning(n, fp32, **cur)
+    entry = dict(n=n, form="fp32" if fp32 else "fp64", k=p.k, **cur, **rec)
+    print(f"tuned n={n} {entry['form']}: " + ", ".join(f"{k}={cur[k]}" for k in ks.TUNING_KEYS), file=log,
+          flush=True)
+    return entry
 
 
 def tune(ns=ALL_N, forms=(False, True), reps: int = 7, log=sys.stderr) -> dict:
-    entries = []
-    for n in ns:
-        for fp32 in forms:
-            e = tune_one(n, fp32, reps)
-            entries.append(e)
-            print(f"tuned n={n} {e['form']}: fwd passes {e['fwd_tail_passes']}, bwd passes "
-                  f"{e['bwd_tail_passes']}, switch {e['fp32_switch_columns']}", file=log, flush=True)
-    return dict(version=1, device=torch.cuda.get_device_name(0), entries=entries)
+    entries = [tune_one(n, fp32, reps, log) for n in ns for fp32 in forms]
+    return dict(version=2, device=torch.cuda.get_device_name(0), entries=entries)
 
 
 def main():

@@ -687,7 +687,7 @@ __device__ __forceinline__ void stage_inputs(const FwdArgs &a, int64_t blk, doub
 // one forward level, one unit per G lanes, many workgroups
 // With FOLD, the last unit of an odd level also folds the last column in
 // (its statistics join its block's slot; the level's fold slot is set neutral).
-template <int N, int MM, bool RAW, class T, class TIN, bool BATCH, bool FOLD = false>
+template <int N, int MM, bool RAW, class T, class TIN, bool BATCH, bool FOLD = false, bool STG = true>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(wf_min_waves(N)))) void k_forward(
     FwdArgs a0, const FwdArgs *tab, BlockMap bm) {
     const FwdArgs &a = BATCH ? tab[bm.item[blockIdx.x]] : a0;
@@ -696,7 +696,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(wf_min_w
     bool bad = false, nonfinite = false;
     double dmin = INFINITY, dmax = 0.0;
     const int64_t t = blk * Geo<N>::UPB + g.ui;
-    if constexpr (Stage<N, MM, RAW>::ON) {
+    if constexpr (STG && Stage<N, MM, RAW>::ON) {
         __shared__ double lds[Stage<N, MM, RAW>::WORDS];
         FwdArgs v = a;
         stage_inputs<N, MM, RAW, TIN>(a, blk, lds, v);
@@ -1069,11 +1069,11 @@ struct BwdTailBlock {
     static constexpr int TB = (8 * Geo<N>::UPW * PER * 8 <= 96 * 1024) ? 512 : kBlock;
 };
 
-template <int N, int MM, bool RAW, class T, class TIN>
+template <int N, int MM, bool RAW, class T, class TIN, bool STG = true>
 static void launch_fwd_t(const FwdArgs &a, hipStream_t s) {
     const int64_t blocks = (a.units + Geo<N>::UPB - 1) / Geo<N>::UPB;
-    hipLaunchKernelGGL((k_forward<N, MM, RAW, T, TIN, false>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
-                       a, nullptr, BlockMap{});
+    hipLaunchKernelGGL((k_forward<N, MM, RAW, T, TIN, false, false, STG>), dim3((unsigned)blocks), dim3(kBlock),
+                       0, s, a, nullptr, BlockMap{});
 }
 
 template <int N, int MM, class T, class TIN>
@@ -1088,10 +1088,10 @@ static void launch_fwd_multi_t(const FwdMultiArgs &a, hipStream_t s) {
     hipLaunchKernelGGL((k_fwd_multi<N, MM, RAW0, T, TIN>), dim3((unsigned)a.groups), dim3(kBlock), 0, s, a);
 }
 
-template <int N, int MM, bool RAW, class T, class TIN>
+template <int N, int MM, bool RAW, class T, class TIN, bool STG = true>
 static void launch_fwd_bt(const FwdArgs *tab, BlockMap bm, int64_t blocks, hipStream_t s) {
-    hipLaunchKernelGGL((k_forward<N, MM, RAW, T, TIN, true>), dim3((unsigned)blocks), dim3(kBlock), 0, s,
-                       FwdArgs{}, tab, bm);
+    hipLaunchKernelGGL((k_forward<N, MM, RAW, T, TIN, true, false, STG>), dim3((unsigned)blocks), dim3(kBlock),
+                       0, s, FwdArgs{}, tab, bm);
 }
 
 template <int N, int MM, bool RAW, class T, class TIN>
@@ -1200,6 +1200,17 @@ constexpr KernelSet make_set() {
     return s;
 }
 
-#define KS_SETS(N) make_set<N, (N + 1) / 2>(), make_set<N, N>(), make_set<N, 2 * N>()
+// forward variant 1: the level-0 kernels without LDS staging (where the
+// default stages), everything else as the default
+template <int N, int MM>
+constexpr KernelSet make_set_unstaged() {
+    KernelSet s = make_set<N, MM>();
+    s.fwd_raw[0] = &launch_fwd_t<N, MM, true, double, double, false>;
+    s.fwd_raw[1] = &launch_fwd_t<N, MM, true, float, double, false>;
+    s.fwd_raw_b[0] = &launch_fwd_bt<N, MM, true, double, double, false>;
+    s.fwd_raw_b[1] = &launch_fwd_bt<N, MM, true, float, double, false>;
+    s.fv = 1;
+    return s;
+}
 
 }  // namespace ks

@@ -13,14 +13,18 @@
 
 namespace ks {
 
-template <int N>
+// records per backward workgroup, the default of each n (measured): one
+// wavefront per record up to n = 12 (an R row fits its lanes, at most two P
+// tiles), two up to n = 24, all four above (n = 32 loses with two: its LDS
+// then allows one workgroup per CU).  Other counts are compiled as variants
+// the autotuner can pick.
+constexpr int blk_rpw(int n) { return (n <= 12) ? 4 : (n <= 24) ? 2 : 1; }
+
+template <int N, int RPW_ = blk_rpw(N)>
 struct BGeo {
     static constexpr int W = 3 * N + 1;                    // columns of an R row
     static constexpr int TBB = 256;                        // backward workgroup (four MFMA wavefronts)
-    // records per workgroup (measured): one wavefront per record up to n = 12
-    // (an R row fits its lanes, at most two P tiles), two up to n = 24, all four
-    // above (n = 32 loses with two: its LDS then allows one workgroup per CU)
-    static constexpr int RPW = (N <= 12) ? 4 : (N <= 24) ? 2 : 1;
+    static constexpr int RPW = RPW_;                       // records per workgroup
     static constexpr int UT = TBB / RPW;                   // threads per record
     static constexpr int WPU = UT / 64;                    // wavefronts per record
     static constexpr int RREC = N * (3 * N + 1);
@@ -77,10 +81,10 @@ __device__ __forceinline__ void rec_sync() {
 //     levels, S_ii is symmetrized on the way out.
 // BGeo<N>::UT threads per record (the record's own LDS region sm); every
 // thread of the workgroup must call it the same number of times.
-template <int N, bool DO_Y, bool DO_COV, class TR>
+template <int N, bool DO_Y, bool DO_COV, class TR, int RPW = blk_rpw(N)>
 __device__ __forceinline__ void blk_bwd_unit(const BwdArgs &a, int l, int64_t t, int64_t units,
                                              bool store_s, double *sm) {
-    using BG = BGeo<N>;
+    using BG = BGeo<N, RPW>;
     using SM = BSmem<N, DO_COV>;
     constexpr int W = BG::W;
     constexpr int LR = SM::LR, LT = SM::LT;
@@ -319,32 +323,30 @@ __device__ __forceinline__ void blk_bwd_unit(const BwdArgs &a, int l, int64_t t,
     rec_sync<WPU>();
 }
 
-template <int N, bool DO_Y, bool DO_COV, class TR, bool BATCH>
-__global__ __launch_bounds__(BGeo<N>::TBB) void k_blk_backward(BwdArgs a0, const BwdArgs *tab,
-                                                               BlockMap bm) {
+template <int N, bool DO_Y, bool DO_COV, class TR, bool BATCH, int RPW>
+__global__ __launch_bounds__(256) void k_blk_backward(BwdArgs a0, const BwdArgs *tab, BlockMap bm) {
     const BwdArgs &a = BATCH ? tab[bm.item[blockIdx.x]] : a0;
-    using BG = BGeo<N>;
+    using BG = BGeo<N, RPW>;
     constexpr int PER = BSmem<N, DO_COV>::PER;
     __shared__ double sm[BG::RPW * PER];
     const int l = BATCH ? bm.level[blockIdx.x] : a.level;
     const int64_t blk = BATCH ? bm.blk[blockIdx.x] : (int64_t)blockIdx.x;
     const int u = threadIdx.x / BG::UT;
-    blk_bwd_unit<N, DO_Y, DO_COV, TR>(a, l, blk * BG::RPW + u, (a.Nl[l] + 1) / 2, a.store_s && l >= 1,
-                                      sm + u * PER);
+    blk_bwd_unit<N, DO_Y, DO_COV, TR, RPW>(a, l, blk * BG::RPW + u, (a.Nl[l] + 1) / 2, a.store_s && l >= 1,
+                                           sm + u * PER);
 }
 
-template <int N, bool DO_Y, bool DO_COV, bool BATCH>
-__global__ __launch_bounds__(BGeo<N>::TBB) void k_blk_bwd_tail(BwdArgs a0, const BwdArgs *tab,
-                                                               BlockMap bm) {
+template <int N, bool DO_Y, bool DO_COV, bool BATCH, int RPW>
+__global__ __launch_bounds__(256) void k_blk_bwd_tail(BwdArgs a0, const BwdArgs *tab, BlockMap bm) {
     const BwdArgs &a = BATCH ? tab[bm.item[blockIdx.x]] : a0;
-    using BG = BGeo<N>;
+    using BG = BGeo<N, RPW>;
     constexpr int PER = BSmem<N, DO_COV>::PER;
     __shared__ double sm[BG::RPW * PER];
     const int u = threadIdx.x / BG::UT;
     for (int l = a.level; l >= a.l_lo; --l) {
         const int64_t units = (a.Nl[l] + 1) / 2;
         for (int64_t t0 = 0; t0 < units; t0 += BG::RPW)
-            blk_bwd_unit<N, DO_Y, DO_COV, double>(a, l, t0 + u, units, a.store_s && l >= 1, sm + u * PER);
+            blk_bwd_unit<N, DO_Y, DO_COV, double, RPW>(a, l, t0 + u, units, a.store_s && l >= 1, sm + u * PER);
         __syncthreads();  // the next level reads what this workgroup wrote: workgroup scope suffices
     }
 }
@@ -356,9 +358,9 @@ __global__ __launch_bounds__(BGeo<N>::TBB) void k_blk_bwd_tail(BwdArgs a0, const
 // reads (i +- 2^l, and the S block one of them stored) lies inside that range,
 // where this workgroup wrote it one level up, or on its ends, which earlier
 // launches wrote; so levels are separated by workgroup barriers only.
-template <int N, bool DO_Y, bool DO_COV, class TR>
-__global__ __launch_bounds__(BGeo<N>::TBB) void k_blk_bwd_multi(BwdArgs a) {
-    using BG = BGeo<N>;
+template <int N, bool DO_Y, bool DO_COV, class TR, int RPW>
+__global__ __launch_bounds__(256) void k_blk_bwd_multi(BwdArgs a) {
+    using BG = BGeo<N, RPW>;
     constexpr int PER = BSmem<N, DO_COV>::PER;
     __shared__ double sm[BG::RPW * PER];
     const int u = threadIdx.x / BG::UT;
@@ -369,53 +371,77 @@ __global__ __launch_bounds__(BGeo<N>::TBB) void k_blk_bwd_multi(BwdArgs a) {
         const int64_t lo = c * span;
         const int64_t hi = lo + span < recs ? lo + span : recs;
         for (int64_t t0 = lo; t0 < hi; t0 += BG::RPW)
-            blk_bwd_unit<N, DO_Y, DO_COV, TR>(a, l, t0 + u, hi, a.store_s && l >= 1, sm + u * PER);
+            blk_bwd_unit<N, DO_Y, DO_COV, TR, RPW>(a, l, t0 + u, hi, a.store_s && l >= 1, sm + u * PER);
         __syncthreads();  // the next level reads what this workgroup's records wrote
     }
 }
 
 // -------------------------------------------------------------- dispatch
 
-template <int N, bool Y, bool COV, class TR>
+template <int N, bool Y, bool COV, class TR, int RPW>
 static void launch_blk_bwd_t(const BwdArgs &a, hipStream_t s) {
     const int64_t units = (a.Nl[a.level] + 1) / 2;
-    const int64_t blocks = (units + BGeo<N>::RPW - 1) / BGeo<N>::RPW;
-    hipLaunchKernelGGL((k_blk_backward<N, Y, COV, TR, false>), dim3((unsigned)blocks), dim3(BGeo<N>::TBB), 0,
-                       s, a, nullptr, BlockMap{});
+    const int64_t blocks = (units + RPW - 1) / RPW;
+    hipLaunchKernelGGL((k_blk_backward<N, Y, COV, TR, false, RPW>), dim3((unsigned)blocks), dim3(256), 0, s, a,
+                       nullptr, BlockMap{});
 }
-template <int N, bool Y, bool COV, class TR>
+template <int N, bool Y, bool COV, class TR, int RPW>
 static void launch_blk_bwd_bt(const BwdArgs *tab, BlockMap bm, int64_t blocks, hipStream_t s) {
-    hipLaunchKernelGGL((k_blk_backward<N, Y, COV, TR, true>), dim3((unsigned)blocks), dim3(BGeo<N>::TBB), 0,
-                       s, BwdArgs{}, tab, bm);
-}
-template <int N, bool Y, bool COV>
-static void launch_blk_bwd_tail_t(const BwdArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((k_blk_bwd_tail<N, Y, COV, false>), dim3(1), dim3(BGeo<N>::TBB), 0, s, a, nullptr,
-                       BlockMap{});
-}
-template <int N, bool Y, bool COV>
-static void launch_blk_bwd_tail_bt(const BwdArgs *tab, BlockMap bm, int64_t blocks, hipStream_t s) {
-    hipLaunchKernelGGL((k_blk_bwd_tail<N, Y, COV, true>), dim3((unsigned)blocks), dim3(BGeo<N>::TBB), 0, s,
+    hipLaunchKernelGGL((k_blk_backward<N, Y, COV, TR, true, RPW>), dim3((unsigned)blocks), dim3(256), 0, s,
                        BwdArgs{}, tab, bm);
 }
-
-template <int N, bool Y, bool COV, class TR>
+template <int N, bool Y, bool COV, int RPW>
+static void launch_blk_bwd_tail_t(const BwdArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL((k_blk_bwd_tail<N, Y, COV, false, RPW>), dim3(1), dim3(256), 0, s, a, nullptr,
+                       BlockMap{});
+}
+template <int N, bool Y, bool COV, int RPW>
+static void launch_blk_bwd_tail_bt(const BwdArgs *tab, BlockMap bm, int64_t blocks, hipStream_t s) {
+    hipLaunchKernelGGL((k_blk_bwd_tail<N, Y, COV, true, RPW>), dim3((unsigned)blocks), dim3(256), 0, s,
+                       BwdArgs{}, tab, bm);
+}
+template <int N, bool Y, bool COV, class TR, int RPW>
 static void launch_blk_bwd_multi_t(const BwdArgs &a, hipStream_t s) {
     const int64_t recs = (a.Nl[a.l_lo] + 1) / 2;
     const int64_t span = (int64_t)1 << (a.level - a.l_lo);
     const int64_t blocks = (recs + span - 1) / span;
-    hipLaunchKernelGGL((k_blk_bwd_multi<N, Y, COV, TR>), dim3((unsigned)blocks), dim3(BGeo<N>::TBB), 0, s, a);
+    hipLaunchKernelGGL((k_blk_bwd_multi<N, Y, COV, TR, RPW>), dim3((unsigned)blocks), dim3(256), 0, s, a);
 }
 
-template <int N>
-constexpr void set_blk_bwd_multi(KernelSet &s) {
-    s.bwd_multi[BWD_Y][0] = &launch_blk_bwd_multi_t<N, true, false, double>;
-    s.bwd_multi[BWD_Y][1] = &launch_blk_bwd_multi_t<N, true, false, float>;
-    s.bwd_multi[BWD_COV][0] = &launch_blk_bwd_multi_t<N, false, true, double>;
-    s.bwd_multi[BWD_COV][1] = &launch_blk_bwd_multi_t<N, false, true, float>;
-    s.bwd_multi[BWD_BOTH][0] = &launch_blk_bwd_multi_t<N, true, true, double>;
-    s.bwd_multi[BWD_BOTH][1] = &launch_blk_bwd_multi_t<N, true, true, float>;
-    s.rpp_multi = BGeo<N>::RPW;
+// Every backward entry of a kernel set from the MFMA family with RPW records
+// per workgroup (all three modes, both record types, single / batched /
+// tail / group launches), so every mode comes from one family.
+template <int N, int RPW>
+constexpr void set_blk_bwd(KernelSet &s) {
+    s.bwd[BWD_Y][0] = &launch_blk_bwd_t<N, true, false, double, RPW>;
+    s.bwd[BWD_Y][1] = &launch_blk_bwd_t<N, true, false, float, RPW>;
+    s.bwd[BWD_COV][0] = &launch_blk_bwd_t<N, false, true, double, RPW>;
+    s.bwd[BWD_COV][1] = &launch_blk_bwd_t<N, false, true, float, RPW>;
+    s.bwd[BWD_BOTH][0] = &launch_blk_bwd_t<N, true, true, double, RPW>;
+    s.bwd[BWD_BOTH][1] = &launch_blk_bwd_t<N, true, true, float, RPW>;
+    s.bwd_tail[BWD_Y] = &launch_blk_bwd_tail_t<N, true, false, RPW>;
+    s.bwd_tail[BWD_COV] = &launch_blk_bwd_tail_t<N, false, true, RPW>;
+    s.bwd_tail[BWD_BOTH] = &launch_blk_bwd_tail_t<N, true, true, RPW>;
+    s.bwd_b[BWD_Y][0] = &launch_blk_bwd_bt<N, true, false, double, RPW>;
+    s.bwd_b[BWD_Y][1] = &launch_blk_bwd_bt<N, true, false, float, RPW>;
+    s.bwd_b[BWD_COV][0] = &launch_blk_bwd_bt<N, false, true, double, RPW>;
+    s.bwd_b[BWD_COV][1] = &launch_blk_bwd_bt<N, false, true, float, RPW>;
+    s.bwd_b[BWD_BOTH][0] = &launch_blk_bwd_bt<N, true, true, double, RPW>;
+    s.bwd_b[BWD_BOTH][1] = &launch_blk_bwd_bt<N, true, true, float, RPW>;
+    s.bwd_tail_b[BWD_Y] = &launch_blk_bwd_tail_bt<N, true, false, RPW>;
+    s.bwd_tail_b[BWD_COV] = &launch_blk_bwd_tail_bt<N, false, true, RPW>;
+    s.bwd_tail_b[BWD_BOTH] = &launch_blk_bwd_tail_bt<N, true, true, RPW>;
+    s.bwd_multi[BWD_Y][0] = &launch_blk_bwd_multi_t<N, true, false, double, RPW>;
+    s.bwd_multi[BWD_Y][1] = &launch_blk_bwd_multi_t<N, true, false, float, RPW>;
+    s.bwd_multi[BWD_COV][0] = &launch_blk_bwd_multi_t<N, false, true, double, RPW>;
+    s.bwd_multi[BWD_COV][1] = &launch_blk_bwd_multi_t<N, false, true, float, RPW>;
+    s.bwd_multi[BWD_BOTH][0] = &launch_blk_bwd_multi_t<N, true, true, double, RPW>;
+    s.bwd_multi[BWD_BOTH][1] = &launch_blk_bwd_multi_t<N, true, true, float, RPW>;
+    for (int q = 0; q < 3; ++q) {
+        s.upb_bwd[q] = RPW;
+        s.upb_bwd_tail[q] = 0;
+    }
+    s.rpp_multi = RPW;
 }
 
 template <int N, int MM>
@@ -430,11 +456,8 @@ constexpr KernelSet make_blk_set_base() {
                       &launch_wg_fold_t<N, MM, false, double, float>},
                      &launch_wg_fwd_tail_t<N, MM, true>,
                      &launch_wg_fwd_tail_t<N, MM, false>,
-                     {{&launch_blk_bwd_t<N, true, false, double>, &launch_blk_bwd_t<N, true, false, float>},
-                      {&launch_blk_bwd_t<N, false, true, double>, &launch_blk_bwd_t<N, false, true, float>},
-                      {&launch_blk_bwd_t<N, true, true, double>, &launch_blk_bwd_t<N, true, true, float>}},
-                     {&launch_blk_bwd_tail_t<N, true, false>, &launch_blk_bwd_tail_t<N, false, true>,
-                      &launch_blk_bwd_tail_t<N, true, true>},
+                     {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}},  // backward: set_blk_bwd
+                     {nullptr, nullptr, nullptr},
                      {&launch_wg_fwd_bt<N, MM, true, double, double>, &launch_wg_fwd_bt<N, MM, true, float, double>},
                      {&launch_wg_fwd_bt<N, MM, false, double, double>, &launch_wg_fwd_bt<N, MM, false, float, float>,
                       &launch_wg_fwd_bt<N, MM, false, double, float>},
@@ -443,27 +466,31 @@ constexpr KernelSet make_blk_set_base() {
                       &launch_wg_fold_bt<N, MM, false, double, float>},
                      &launch_wg_fwd_tail_bt<N, MM, true>,
                      &launch_wg_fwd_tail_bt<N, MM, false>,
-                     {{&launch_blk_bwd_bt<N, true, false, double>, &launch_blk_bwd_bt<N, true, false, float>},
-                      {&launch_blk_bwd_bt<N, false, true, double>, &launch_blk_bwd_bt<N, false, true, float>},
-                      {&launch_blk_bwd_bt<N, true, true, double>, &launch_blk_bwd_bt<N, true, true, float>}},
-                     {&launch_blk_bwd_tail_bt<N, true, false>, &launch_blk_bwd_tail_bt<N, false, true>,
-                      &launch_blk_bwd_tail_bt<N, true, true>},
+                     {{nullptr, nullptr}, {nullptr, nullptr}, {nullptr, nullptr}},
+                     {nullptr, nullptr, nullptr},
                      1,
                      1,
-                     {BGeo<N>::RPW, BGeo<N>::RPW, BGeo<N>::RPW},
+                     {0, 0, 0},
                      {0, 0, 0},
                      {&launch_wg_fwd_fold_t<N, MM, double, double>, &launch_wg_fwd_fold_t<N, MM, float, float>,
                       &launch_wg_fwd_fold_t<N, MM, double, float>}};
 }
 
-template <int N, int MM>
+// Forward on the two-dimensional tiling, backward on MFMA with RPW records
+// per workgroup (backward variant bv of the set)
+template <int N, int MM, int RPW, int BV>
 constexpr KernelSet make_blk_set() {
     KernelSet s = make_blk_set_base<N, MM>();
-    set_blk_bwd_multi<N>(s);
+    set_blk_bwd<N, RPW>(s);
+    s.bv = BV;
     return s;
 }
 
-#define KS_BLK_SETS(N) make_blk_set<N, wg_mm_small(N)>(), make_blk_set<N, N>()
+// the default of each n first, then its backward variants
+#define KS_BLK_SETS_MM(N, MM)                                                                         \
+    make_blk_set<N, MM, blk_rpw(N), 0>(), make_blk_set<N, MM, (blk_rpw(N) == 1 ? 2 : 1), 1>()
+#define KS_BLK_SETS(N) KS_BLK_SETS_MM(N, wg_mm_small(N)), KS_BLK_SETS_MM(N, N)
+#define KS_BLK_SETS_ONE(N) make_blk_set<N, wg_mm_small(N), 1, 0>(), make_blk_set<N, N, 1, 0>()
 
 // Wavefront-family forward (register-resident units, no barriers) with the
 // workgroup-family backward (MFMA SelInv; any n: rows, columns and inner
@@ -472,36 +499,24 @@ constexpr KernelSet make_blk_set() {
 // rho_i | R_i,left] (FP32 records in the first half of their slot), so the
 // halves combine freely.  Every backward mode (states only, covariances only,
 // both) comes from the same family, so the states of a states-only pass are
-// bitwise those of a full pass.
-template <int N, int MM>
+// bitwise those of a full pass.  Backward variants: RPW records per
+// workgroup; forward variant 1: the level-0 kernel without LDS staging.
+template <int N, int MM, int RPW, int BV>
 constexpr KernelSet make_hyb_set() {
     KernelSet s = make_set<N, MM>();
-    s.bwd[0][0] = &launch_blk_bwd_t<N, true, false, double>;
-    s.bwd[0][1] = &launch_blk_bwd_t<N, true, false, float>;
-    s.bwd[1][0] = &launch_blk_bwd_t<N, false, true, double>;
-    s.bwd[1][1] = &launch_blk_bwd_t<N, false, true, float>;
-    s.bwd[2][0] = &launch_blk_bwd_t<N, true, true, double>;
-    s.bwd[2][1] = &launch_blk_bwd_t<N, true, true, float>;
-    s.bwd_tail[0] = &launch_blk_bwd_tail_t<N, true, false>;
-    s.bwd_tail[1] = &launch_blk_bwd_tail_t<N, false, true>;
-    s.bwd_tail[2] = &launch_blk_bwd_tail_t<N, true, true>;
-    s.bwd_b[0][0] = &launch_blk_bwd_bt<N, true, false, double>;
-    s.bwd_b[0][1] = &launch_blk_bwd_bt<N, true, false, float>;
-    s.bwd_b[1][0] = &launch_blk_bwd_bt<N, false, true, double>;
-    s.bwd_b[1][1] = &launch_blk_bwd_bt<N, false, true, float>;
-    s.bwd_b[2][0] = &launch_blk_bwd_bt<N, true, true, double>;
-    s.bwd_b[2][1] = &launch_blk_bwd_bt<N, true, true, float>;
-    s.bwd_tail_b[0] = &launch_blk_bwd_tail_bt<N, true, false>;
-    s.bwd_tail_b[1] = &launch_blk_bwd_tail_bt<N, false, true>;
-    s.bwd_tail_b[2] = &launch_blk_bwd_tail_bt<N, true, true>;
-    for (int q = 0; q < 3; ++q) {
-        s.upb_bwd[q] = BGeo<N>::RPW;
-        s.upb_bwd_tail[q] = 0;
-    }
-    set_blk_bwd_multi<N>(s);
+    set_blk_bwd<N, RPW>(s);
+    s.bv = BV;
     return s;
 }
 
-#define KS_HYB_SETS(N) make_hyb_set<N, (N + 1) / 2>(), make_hyb_set<N, N>(), make_hyb_set<N, 2 * N>()
+#define KS_HYB_SETS_MM(N, MM)                                                                         \
+    make_hyb_set<N, MM, 4, 0>(), make_hyb_set<N, MM, 2, 1>(), make_hyb_set<N, MM, 1, 2>(),            \
+        make_set_unstaged<N, MM>()
+#define KS_HYB_SETS(N) KS_HYB_SETS_MM(N, (N + 1) / 2), KS_HYB_SETS_MM(N, N), KS_HYB_SETS_MM(N, 2 * N)
+
+// Wavefront family throughout (n = 1, 2, 3, 5), with the MFMA backward as
+// backward variant 1 and the unstaged level 0 as forward variant 1
+#define KS_SETS_MM(N, MM) make_set<N, MM>(), make_hyb_set<N, MM, 4, 1>(), make_set_unstaged<N, MM>()
+#define KS_SETS(N) KS_SETS_MM(N, (N + 1) / 2), KS_SETS_MM(N, N), KS_SETS_MM(N, 2 * N)
 
 }  // namespace ks

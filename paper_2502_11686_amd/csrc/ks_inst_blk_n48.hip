@@ -6,7 +6,7 @@ namespace ks {
 // host-only table (a function-local static is never emitted for the device)
 const KernelSetList &list_blk_n48() {
     static const KernelSet sets[] = {
-    KS_BLK_SETS(48),
+    KS_BLK_SETS_ONE(48),  // two records per workgroup would exceed the LDS
     };
     static const KernelSetList list = {sets, sizeof(sets) / sizeof(sets[0])};
     return list;

@@ -8,8 +8,8 @@ const KernelSetList &list_n1_3() {
     static const KernelSet sets[] = {
     make_set<1, 1>(),
     make_set<1, 2>(),
-    KS_SETS(2),
-    KS_SETS(3),
+    make_set<2, 1>(), make_set<2, 2>(), make_set<2, 4>(),
+    make_set<3, 2>(), make_set<3, 3>(), make_set<3, 6>(),
     };
     static const KernelSetList list = {sets, sizeof(sets) / sizeof(sets[0])};
     return list;

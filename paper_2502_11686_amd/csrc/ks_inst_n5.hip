@@ -1,5 +1,6 @@
-// ks_inst_n5.hip -- kernel instantiations for one group of state dimensions.
-#include "ks_device.h"
+// ks_inst_n5.hip -- kernel instantiations for n = 5: wavefront family, with
+// the MFMA backward and the unstaged level 0 as tunable variants.
+#include "ks_device_blk.h"
 
 namespace ks {
 

@@ -155,6 +155,9 @@ struct KernelSet {
     BwdFn bwd_multi[3][2];
     int upb_multi;    // units per pass of a forward group workgroup
     int rpp_multi;    // records per pass of a backward group workgroup
+    // which compiled variant of the (n, observation class) this set is: its
+    // forward half (fv) and backward half (bv); 0 = the default of n
+    int fv, bv;
 };
 
 struct KernelSetList {
@@ -162,8 +165,14 @@ struct KernelSetList {
     int64_t count;
 };
 
-// nullptr when (n, m) has no instantiation
+// nullptr when (n, m) has no instantiation (the default variants)
 const KernelSet *find_kernels(int n, int m);
+// the set of (n, m) with forward variant fv and backward variant bv (a
+// composed set with a stable address), or nullptr when either variant does
+// not exist
+const KernelSet *find_kernels(int n, int m, int fv, int bv);
+// number of forward / backward variants compiled for (n, m) (0 if none)
+int kernel_variants(int n, int m, bool backward);
 
 // One states + covariances pass (ks_smooth_cov's kernels and schedule) on a
 // workspace the caller provides, without a plan object kept or any stream,

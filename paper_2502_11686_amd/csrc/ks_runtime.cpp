@@ -287,6 +287,7 @@ struct Tuning {
     int32_t fwd_passes, bwd_passes;
     int64_t switch_cols;
     int32_t fwd_group, fwd_group_from, bwd_group, bwd_group_from;
+    int32_t fwd_variant, bwd_variant;
 };
 constexpr int kTuneMaxN = 64;
 std::mutex g_tune_mu;
@@ -294,7 +295,7 @@ Tuning g_tune[kTuneMaxN + 1][2];
 bool g_tune_set[kTuneMaxN + 1][2];
 
 Tuning tuning_for(int n, int precision) {
-    Tuning t{2, 2, 1024, 1, 1, 1, 1};
+    Tuning t{2, 2, 1024, 1, 1, 1, 1, 0, 0};
     {
         std::lock_guard<std::mutex> lock(g_tune_mu);
         if (n >= 0 && n <= kTuneMaxN && precision >= 0 && precision < 2 && g_tune_set[n][precision])
@@ -306,7 +307,17 @@ Tuning tuning_for(int n, int precision) {
     if (const char *e = std::getenv("KS_FWD_GROUP_FROM")) t.fwd_group_from = std::atoi(e);
     if (const char *e = std::getenv("KS_BWD_GROUP")) t.bwd_group = std::atoi(e);
     if (const char *e = std::getenv("KS_BWD_GROUP_FROM")) t.bwd_group_from = std::atoi(e);
+    if (const char *e = std::getenv("KS_FWD_VARIANT")) t.fwd_variant = std::atoi(e);
+    if (const char *e = std::getenv("KS_BWD_VARIANT")) t.bwd_variant = std::atoi(e);
     return t;
+}
+
+// the kernel set of a problem under the tuning of its (n, form): the tuned
+// forward and backward variants, or the defaults where a variant does not exist
+const ks::KernelSet *tuned_kernels(const ks_desc &d) {
+    const Tuning tu = tuning_for(d.n, d.precision);
+    const ks::KernelSet *k = ks::find_kernels(d.n, d.m, tu.fwd_variant, tu.bwd_variant);
+    return k ? k : ks::find_kernels(d.n, d.m);
 }
 
 // the level schedule of one problem: FP32 levels, first forward tail level,
@@ -581,7 +592,8 @@ ks_status ks_create(const ks_desc *desc, void *workspace, size_t ws_bytes, void 
     if (!out) return KS_E_ARG;
     *out = nullptr;
     if (!valid_desc(desc)) return KS_E_ARG;
-    const ks::KernelSet *kset = ks::find_kernels(desc->n, desc->m);
+    if (!ks::find_kernels(desc->n, desc->m)) return KS_E_ARG;
+    const ks::KernelSet *kset = tuned_kernels(*desc);
     if (!kset) return KS_E_ARG;
     Layout lo;
     if (!make_layout(desc, kset, &lo)) return KS_E_ARG;
@@ -731,11 +743,12 @@ ks_status ks_set_tuning(int32_t n, int32_t precision, const ks_tuning *t) {
     if (n < 1 || n > kTuneMaxN || (precision != KS_FP64 && precision != KS_FP32_FORM) || !t ||
         t->fwd_tail_passes < 0 || t->bwd_tail_passes < 0 || t->fp32_switch_columns < 1 || t->fwd_group < 1 ||
         t->fwd_group > 8 || t->fwd_group_from < 0 || t->bwd_group < 1 || t->bwd_group > 8 ||
-        t->bwd_group_from < 0)
+        t->bwd_group_from < 0 || t->fwd_variant < 0 || t->bwd_variant < 0)
         return KS_E_ARG;
     std::lock_guard<std::mutex> lock(g_tune_mu);
     g_tune[n][precision] = Tuning{t->fwd_tail_passes, t->bwd_tail_passes, t->fp32_switch_columns, t->fwd_group,
-                                  t->fwd_group_from, t->bwd_group, t->bwd_group_from};
+                                  t->fwd_group_from, t->bwd_group, t->bwd_group_from, t->fwd_variant,
+                                  t->bwd_variant};
     g_tune_set[n][precision] = true;
     return KS_OK;
 }
@@ -752,7 +765,13 @@ ks_status ks_get_tuning(int32_t n, int32_t precision, ks_tuning *out) {
     out->fwd_group_from = t.fwd_group_from;
     out->bwd_group = t.bwd_group;
     out->bwd_group_from = t.bwd_group_from;
+    out->fwd_variant = t.fwd_variant;
+    out->bwd_variant = t.bwd_variant;
     return KS_OK;
+}
+
+int32_t ks_kernel_variants(int32_t n, int32_t m, int32_t backward) {
+    return ks::kernel_variants(n, m, backward != 0);
 }
 
 ks_status ks_plan_schedule(const ks_plan *p, int32_t *fp32_levels, int32_t *fwd_tail_level,
@@ -810,8 +829,8 @@ ks_status smooth_cov_on(const ks_desc *desc, void *workspace, size_t ws_bytes, h
                         const double *G, const double *o, const double *C, double *u_out,
                         double *cov_out) {
     if (!valid_desc(desc) || !u_out || !cov_out) return KS_E_ARG;
-    const KernelSet *kset = find_kernels(desc->n, desc->m);
-    if (!kset) return KS_E_ARG;
+    if (!find_kernels(desc->n, desc->m)) return KS_E_ARG;
+    const KernelSet *kset = tuned_kernels(*desc);
     ks_plan p;  // host state on the stack: no graph, no timing events
     if (!make_layout(desc, kset, &p.lo)) return KS_E_ARG;
     if (!workspace || (reinterpret_cast<uintptr_t>(workspace) % kAlign) != 0 || ws_bytes < p.lo.total)
@@ -1170,7 +1189,7 @@ static ks_status batch_setup(int32_t count, const ks_desc *descs, ks_batch *b, s
         BatchProblem &pr = b->probs[i];
         pr.d = descs[i];
         if (!valid_desc(&pr.d)) return KS_E_ARG;
-        pr.kset = ks::find_kernels(pr.d.n, pr.d.m);
+        pr.kset = ks::find_kernels(pr.d.n, pr.d.m) ? tuned_kernels(pr.d) : nullptr;
         if (!pr.kset) return KS_E_ARG;
         if (!make_layout(&pr.d, pr.kset, &pr.lo)) return KS_E_ARG;
         pr.ws_off = off;
@@ -1592,7 +1611,7 @@ ks_status ks_engine_submit(ks_engine *e, const ks_desc *desc, const ks_io *io, i
     EngReq r{};
     BatchProblem &pr = r.pr;
     pr.d = *desc;
-    pr.kset = ks::find_kernels(desc->n, desc->m);
+    pr.kset = ks::find_kernels(desc->n, desc->m) ? tuned_kernels(*desc) : nullptr;
     if (!pr.kset || !make_layout(desc, pr.kset, &pr.lo)) return KS_E_ARG;
     if (!io->u_out || (want_cov && !io->cov_out)) return KS_E_ARG;
     if (desc->k > 0 && (!io->F || !io->c || !io->K)) return KS_E_ARG;

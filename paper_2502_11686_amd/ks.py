@@ -29,7 +29,7 @@ SYMBOLS = ("ks_workspace_bytes", "ks_supported", "ks_create", "ks_smooth", "ks_c
            "ks_batch_smooth", "ks_batch_destroy", "ks_engine_create", "ks_engine_submit",
            "ks_engine_step", "ks_engine_wait", "ks_engine_retired", "ks_engine_poll", "ks_engine_query", "ks_engine_destroy",
            "ks_set_tuning", "ks_get_tuning", "ks_plan_schedule", "ks_smooth_cov_lag1", "ks_objective",
-           "ks_smooth_cov_static")
+           "ks_smooth_cov_static", "ks_kernel_variants")
 KS_TIME_OFF, KS_TIME_FWD_LEVEL0, KS_TIME_BWD_LEVEL0, KS_TIME_FWD_ALL, KS_TIME_BWD_ALL = range(5)
 
 
@@ -43,12 +43,13 @@ class Tuning(ctypes.Structure):
     _fields_ = [("fwd_tail_passes", ctypes.c_int32), ("bwd_tail_passes", ctypes.c_int32),
                 ("fp32_switch_columns", ctypes.c_int64), ("fwd_group", ctypes.c_int32),
                 ("fwd_group_from", ctypes.c_int32), ("bwd_group", ctypes.c_int32),
-                ("bwd_group_from", ctypes.c_int32)]
+                ("bwd_group_from", ctypes.c_int32), ("fwd_variant", ctypes.c_int32),
+                ("bwd_variant", ctypes.c_int32)]
 
 
 TUNING_KEYS = tuple(f for f, _t in Tuning._fields_)
 TUNING_DEFAULTS = dict(fwd_tail_passes=2, bwd_tail_passes=2, fp32_switch_columns=1024, fwd_group=1,
-                       fwd_group_from=1, bwd_group=1, bwd_group_from=1)
+                       fwd_group_from=1, bwd_group=1, bwd_group_from=1, fwd_variant=0, bwd_variant=0)
 
 
 class Layout(ctypes.Structure):
@@ -147,6 +148,8 @@ def lib():
     L.ks_plan_schedule.restype = ctypes.c_int
     L.ks_plan_schedule.argtypes = [vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                    ctypes.POINTER(ctypes.c_int32)]
+    L.ks_kernel_variants.restype = ctypes.c_int32
+    L.ks_kernel_variants.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
     L.ks_smooth_cov_static.restype = ctypes.c_int
     L.ks_smooth_cov_static.argtypes = [ctypes.POINTER(Desc)] + [dp] * 9 + [vp]
     _lib = L
@@ -188,6 +191,11 @@ def load_tuning(path: str) -> int:
         vals = {k: e.get(k, TUNING_DEFAULTS[k]) for k in TUNING_KEYS}
         set_tuning(e["n"], e["form"] == "fp32", **vals)
     return len(table.get("entries", []))
+
+
+def kernel_variants(n: int, m: int, backward: bool) -> int:
+    """Compiled forward / backward shape variants of (n, m)."""
+    return int(lib().ks_kernel_variants(int(n), int(m), 1 if backward else 0))
 
 
 def make_desc(k: int, n: int, m: int, K_diag: bool, C_diag: bool, fp32: bool = False) -> Desc:
