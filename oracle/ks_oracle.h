@@ -14,6 +14,12 @@
  * Outputs: u_out [k+1][n] (required); cov_out [k+1][n][n] = Sigma_i (optional);
  * lag1_out [k][n][n] = cov(u_i, u_{i+1}) = S_{i,i+1} (optional);
  * resid2_out = squared norm of the whitened least-squares residual (optional).
+ *
+ * kso_smooth forms the covariance outputs by the RTS recursion in
+ * square-root information form over the QR factor R; kso_smooth_rts forms
+ * them by the RTS recursion in information form from the model matrices
+ * (a cross-check; less accurate when A^T cov(e)^{-1} A is ill conditioned).
+ * The states are the same.
  */
 #ifndef KS_ORACLE_H
 #define KS_ORACLE_H
@@ -36,6 +42,11 @@ int kso_smooth(int64_t k, int n, int m, int K_diag, int C_diag,
                const double *K, const double *G, const double *o,
                const double *C, double *u_out, double *cov_out,
                double *lag1_out, double *resid2_out);
+int kso_smooth_rts(int64_t k, int n, int m, int K_diag, int C_diag,
+                   const double *H, const double *F, const double *c,
+                   const double *K, const double *G, const double *o,
+                   const double *C, double *u_out, double *cov_out,
+                   double *lag1_out, double *resid2_out);
 
 #ifdef __cplusplus
 }

@@ -29,9 +29,11 @@ def load(path: str | None = None):
             _build.build()
         lib = ctypes.CDLL(_build.LIB)
     dp = ctypes.POINTER(ctypes.c_double)
-    lib.kso_smooth.restype = ctypes.c_int
-    lib.kso_smooth.argtypes = [ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
-                               ctypes.c_int] + [dp] * 7 + [dp] * 4
+    for name in ("kso_smooth", "kso_smooth_rts"):
+        f = getattr(lib, name)
+        f.restype = ctypes.c_int
+        f.argtypes = [ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                      ctypes.c_int] + [dp] * 7 + [dp] * 4
     if path is None:
         _lib = lib
     return lib
@@ -53,11 +55,16 @@ class OracleError(RuntimeError):
         self.status = status
 
 
-def smooth(p, want_cov: bool = True, want_lag1: bool = False, lib=None, check: bool = True):
+def smooth(p, want_cov: bool = True, want_lag1: bool = False, lib=None, check: bool = True,
+           rts: bool = False):
     """Run the sequential oracle on problem ``p``.
 
     Returns a dict with 'u' [k+1][n], 'cov' [k+1][n][n] (or None), 'lag1'
-    [k][n][n] (or None), 'resid2' and 'status'.
+    [k][n][n] (or None), 'resid2' and 'status'.  Covariances come from the RTS
+    recursion in square-root information form over the QR factor R, or, with
+    rts=True, from the RTS recursion in information form over the model
+    matrices (the cross-check; its error grows with the condition number of
+    the normal matrix).
     """
     lib = lib or load()
     k, n, m = int(p.k), int(p.n), int(p.m)
@@ -66,7 +73,8 @@ def smooth(p, want_cov: bool = True, want_lag1: bool = False, lib=None, check: b
     cov = np.zeros((k + 1, n, n)) if want_cov else None
     lag1 = np.zeros((max(k, 0), n, n)) if want_lag1 else None
     r2 = np.zeros(1)
-    st = lib.kso_smooth(k, n, m, int(bool(p.K_diag)), int(bool(p.C_diag)),
+    fn = lib.kso_smooth_rts if rts else lib.kso_smooth
+    st = fn(k, n, m, int(bool(p.K_diag)), int(bool(p.C_diag)),
                         *[_ptr(a) for a in arrs], _ptr(u), _ptr(cov), _ptr(lag1), _ptr(r2))
     if check and st != OK:
         raise OracleError(st)

@@ -6,7 +6,10 @@ are pinned to references other than themselves:
 * the dense definition against a textbook Kalman filter + RTS smoother in the
   proper-prior special case, and against a QR-based least-squares solve;
 * the sequential oracle against the dense definition over a sweep of k, n, m,
-  covariance layouts and H;
+  covariance layouts and H, with both of its covariance forms (the RTS
+  recursion in square-root form over R, and the RTS recursion in information
+  form over the model matrices, which shares no step with it), and the two
+  forms against each other on long problems;
 * both against closed forms (k = 0), invariants (symmetry, positive
   definiteness, zero gradient of the objective at u_hat, residual identity) and
   a Monte Carlo estimate of cov(u_hat).
@@ -81,24 +84,43 @@ def test_sequential_matches_dense_sweep(n, m):
             for H_mode in ("identity", "random"):
                 p = small(1000 * n + 10 * m + k, k, n, m, cov=cov, H_mode=H_mode)
                 d = dense.smooth(p)
-                o = seq.smooth(p, want_lag1=True)
-                worst_u = max(worst_u, rel_state_err(o["u"], d["u"]))
-                worst_s = max(worst_s, rel_cov_err(o["cov"], d["cov"]))
-                assert abs(o["resid2"] - d["resid2"]) <= 1e-9 * max(1.0, d["resid2"])
-                nn = p.n
-                for i in range(k):
-                    lag = d["S"][i * nn:(i + 1) * nn, (i + 1) * nn:(i + 2) * nn]
-                    assert np.linalg.norm(o["lag1"][i] - lag) <= 1e-9 * np.linalg.norm(lag) + 1e-14
+                for from_rts in (False, True):  # square-root RTS over R; information-form RTS
+                    o = seq.smooth(p, want_lag1=True, rts=from_rts)
+                    worst_u = max(worst_u, rel_state_err(o["u"], d["u"]))
+                    worst_s = max(worst_s, rel_cov_err(o["cov"], d["cov"]))
+                    assert abs(o["resid2"] - d["resid2"]) <= 1e-9 * max(1.0, d["resid2"])
+                    nn = p.n
+                    for i in range(k):
+                        lag = d["S"][i * nn:(i + 1) * nn, (i + 1) * nn:(i + 2) * nn]
+                        assert np.linalg.norm(o["lag1"][i] - lag) <= 1e-9 * np.linalg.norm(lag) + 1e-14
     assert worst_u < 1e-11, worst_u
     assert worst_s < 1e-10, worst_s
 
 
 def test_sequential_matches_kalman_rts_long():
     p = with_prior(small(7, 400, 4, 4, cov="dense"), 5)
-    o = seq.smooth(p)
     xs, Ps = kf_rts(p)
-    assert rel_state_err(o["u"], xs) < 1e-9
-    assert rel_cov_err(o["cov"], Ps) < 1e-8
+    for from_rts in (False, True):
+        o = seq.smooth(p, rts=from_rts)
+        assert rel_state_err(o["u"], xs) < 1e-9
+        assert rel_cov_err(o["cov"], Ps) < 1e-8
+
+
+@pytest.mark.parametrize("n,m,cov,H_mode", [(6, 3, "dense", "identity"), (4, 2, "diag", "random"),
+                                            (12, 6, "dense", "random"), (24, 12, "diag", "identity")])
+def test_rts_recursion_agrees_with_selected_inversion(n, m, cov, H_mode):
+    """The oracle's two covariance forms, the square-root RTS recursion over R
+    and the information-form RTS recursion over the model matrices, on
+    problems too long for the dense definition.  These problems are well
+    conditioned (cond(A^T W A) below 1e6), so the information form, whose
+    error grows with that condition number, agrees to 1e-11."""
+    p = small(77 + n, 3000 if n <= 12 else 400, n, m, cov=cov, H_mode=H_mode)
+    a = seq.smooth(p, want_lag1=True)
+    b = seq.smooth(p, want_lag1=True, rts=True)
+    assert np.array_equal(a["u"], b["u"])
+    assert rel_cov_err(a["cov"], b["cov"]) < 1e-11
+    scale = np.sqrt(np.linalg.norm(a["cov"][:-1], axis=(1, 2)) * np.linalg.norm(a["cov"][1:], axis=(1, 2)))
+    assert np.max(np.linalg.norm(a["lag1"] - b["lag1"], axis=(1, 2)) / scale) < 1e-11
 
 
 def test_k0_closed_form():
