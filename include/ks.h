@@ -274,13 +274,17 @@ ks_status ks_set_tuning(int32_t n, int32_t precision, const ks_tuning *t);
 ks_status ks_get_tuning(int32_t n, int32_t precision, ks_tuning *out);
 /* Number of compiled forward (backward = 0) or backward (backward != 0)
  * variants for state dimension n and observation dimension m, 0 when (n, m)
- * is unsupported.  Variants differ in launch shape only, not in what is
- * computed: forward variant 1 runs level 0 without staging a workgroup's
- * inputs in LDS; backward variants of the MFMA family take 4, 2 or 1 records
- * per workgroup (n <= 12; n = 16, 24: 2 or 1; n = 32: 1 or 2), and for
- * n = 1, 2, 3, 5 backward variant 1 is the MFMA family instead of the
- * wavefront family (then results differ from variant 0 by rounding only).
- * Host-only. */
+ * is unsupported.  Variants compute the same quantities with different
+ * kernels, so results may differ by rounding: forward variant 1 of n <= 12
+ * runs level 0 without staging a workgroup's inputs in LDS; forward variant 1
+ * of n = 32, 48 runs the FP64 forward levels with at least 512 units on the
+ * FP64 matrix cores (blocked Householder QR, compact-WY updates; narrower
+ * levels and the FP32-form levels keep the default kernels) and applies to
+ * problems with diagonal K and C only -- a problem with a dense covariance
+ * takes variant 0 instead; backward variants of the MFMA family take 4, 2 or
+ * 1 records per workgroup (n <= 12; n = 16, 24: 2 or 1; n = 32: 1 or 2), and
+ * for n = 1, 2, 3, 5 backward variant 1 is the MFMA family instead of the
+ * wavefront family.  Host-only. */
 int32_t ks_kernel_variants(int32_t n, int32_t m, int32_t backward);
 /* the plan's schedule: number of FP32 levels, first level of the forward tail
  * launch, lowest level of the backward tail launch (states + covariances) */

@@ -52,9 +52,10 @@ FP32_GATE = 1e-5
 
 def problem_k(n: int) -> int:
     """Trajectory length the table is tuned at: the single-problem workloads'
-    lengths for small n (their top levels are what the tail and group choices
-    act on), shorter where a pass is long."""
-    return 100000 if n <= 8 else (50000 if n <= 12 else (20000 if n <= 16 else 4096))
+    lengths (k = 1e5 at small n, 2e4 for the large blocks), so that both the
+    wide levels (where the shape variants differ most) and the top levels
+    (what the tail and group choices act on) are there."""
+    return 100000 if n <= 8 else (50000 if n <= 12 else 20000)
 
 
 def _problem(n: int):

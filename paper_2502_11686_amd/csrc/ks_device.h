@@ -422,21 +422,22 @@ __device__ __forceinline__ const T *slot(const double *base, int64_t idx, int st
 // ------------------------------------------------------------- forward level
 
 // The last column jl = N_l - 1 of a level with N_l odd (even, no right
-// neighbour): its R row (record t+1), and its Z rows, which touch only column
-// jl - 1, stacked under the step-3 triangle Onew of the last unit t.
-// Inputs are read through `in` (the level's arguments, or a view of them in
-// LDS), results written through `a`.
+// neighbour), in two parts.  fold_col: its R row (record t+1, t the last
+// unit) and its Z rows, which touch only column jl - 1, left in the bottom
+// rows of C2 (Z on the left lanes, zeta on the rhs lane).  fold_merge: those
+// rows stacked under the last unit's step-3 triangle Onew and
+// re-triangularized.  Inputs are read through `in` (the level's arguments, or
+// a view of them in LDS), results written through `a`.
 template <int N, int MM, bool RAW, class T, class TIN>
-__device__ __forceinline__ void fold_part(const FwdArgs &a, const FwdArgs &in, int64_t t, int gl, int gb,
-                                          const LaneRole<N> &L, T (&Onew)[N], double &dmin,
-                                          double &dmax, bool &bad, bool &nonfinite) {
+__device__ __forceinline__ void fold_col(const FwdArgs &a, const FwdArgs &in, int64_t t, int gl, int gb,
+                                         const LaneRole<N> &L, T (&C2)[2 * N], double &dmin, double &dmax,
+                                         bool &bad, bool &nonfinite) {
     using GE = Geo<N>;
     constexpr int RO = RAW ? MM : N;
     constexpr int HC = 2 * N;
-    // the last column jl = N_l - 1 (even, no right neighbour)
     const int64_t jl = a.Nl - 1;
     // C2 = [R~ (its observation block, triangular) ; E+ | E- | eta]
-    T A2[RO], C2[HC];
+    T A2[RO];
     if constexpr (RAW) {
         T cvO[MM], cvE[N];
         load_obs_raw<N, MM>(A2, 0, cvO, jl, L, gl, CUR, 0, in, true);
@@ -455,18 +456,39 @@ __device__ __forceinline__ void fold_part(const FwdArgs &a, const FwdArgs &in, i
     hqr<HC, N, T, N>(C2, gl, gb, 0);
     store_rrow<N>(slot<T>(a.rrows, t + 1, GE::RREC), C2, gl, true);
     diag_stats<N>(C2, L, true, dmin, dmax, nonfinite);
-    // Z rows (left lanes) move onto the right lanes; rhs keeps zeta
-    const int src = gb + ((L.role == RIGHT) ? gl + N + 1 : gl);
+}
+
+// Onew <- triangle of [Onew ; Z | zeta] (pivots on the right lanes); z holds
+// row r of Z | zeta on the right lanes (column rc) and the rhs lane
+template <int N, class T>
+__device__ __forceinline__ void fold_merge(T (&Onew)[N], const T (&z)[N], int gl, int gb) {
     T B2[2 * N];
 #pragma unroll
     for (int r = 0; r < N; ++r) {
-        const T z = bperm(C2[N + r], src);
         B2[r] = Onew[r];
-        B2[N + r] = (L.role == RIGHT || L.role == RHS) ? z : T(0);
+        B2[N + r] = z[r];
     }
     hqr<2 * N, N, T, N>(B2, gl, gb, N);
 #pragma unroll
     for (int r = 0; r < N; ++r) Onew[r] = B2[r];
+}
+
+// both parts in one unit's lanes (Z moved to the right lanes by ds_bpermute)
+template <int N, int MM, bool RAW, class T, class TIN>
+__device__ __forceinline__ void fold_part(const FwdArgs &a, const FwdArgs &in, int64_t t, int gl, int gb,
+                                          const LaneRole<N> &L, T (&Onew)[N], double &dmin,
+                                          double &dmax, bool &bad, bool &nonfinite) {
+    T C2[2 * N];
+    fold_col<N, MM, RAW, T, TIN>(a, in, t, gl, gb, L, C2, dmin, dmax, bad, nonfinite);
+    // Z rows (left lanes) move onto the right lanes; rhs keeps zeta
+    const int src = gb + ((L.role == RIGHT) ? gl + N + 1 : gl);
+    T z[N];
+#pragma unroll
+    for (int r = 0; r < N; ++r) {
+        const T v = bperm(C2[N + r], src);
+        z[r] = (L.role == RIGHT || L.role == RHS) ? v : T(0);
+    }
+    fold_merge<N, T>(Onew, z, gl, gb);
 }
 
 // One unit of a forward level: even column j = 2t and its right neighbour
@@ -475,7 +497,7 @@ __device__ __forceinline__ void fold_part(const FwdArgs &a, const FwdArgs &in, i
 template <int N, int MM, bool RAW, bool INLINE_FOLD, class T, class TIN>
 __device__ __forceinline__ void fwd_unit(const FwdArgs &a, const FwdArgs &src, int64_t t, bool in, int gl,
                                          int gb, double &dmin, double &dmax, bool &bad, bool &nonfinite,
-                                         int64_t t_end = -1) {
+                                         int64_t t_end = -1, T *keep = nullptr) {
     using GE = Geo<N>;
     constexpr int RO = RAW ? MM : N;            // rows of an observation block
     constexpr int HA = RO + N, HB = 2 * RO, HC = 2 * N;
@@ -505,15 +527,28 @@ __device__ __forceinline__ void fwd_unit(const FwdArgs &a, const FwdArgs &src, i
     if constexpr (RAW) {
 #pragma unroll
         for (int r = N; r < HC; ++r) C[r] = T(0);
-        T cvOa[MM], cvOb[MM], cvEa[N], cvEc[N];
-        load_obs_raw<N, MM>(A, 0, cvOa, j, L, gl, CUR, 0, src, valid);
-        load_evol_raw<N>(A, RO, cvEa, j + 1, L, gl, CUR, RIGHT, 0, src, valid);
-        load_obs_raw<N, MM>(B, OB, cvOb, j + 1, L, gl, RIGHT, N, src, valid);
-        load_evol_raw<N>(C, EC, cvEc, j, L, gl, LEFT, CUR, 2 * N + 1, src, valid && j >= 1);
-        whiten<HA, MM>(a.C_diag, A, 0, cvOa, gl, gb, 0, bad);
-        whiten<HA, N>(a.K_diag, A, RO, cvEa, gl, gb, 0, bad);
-        whiten<HB, MM>(a.C_diag, B, OB, cvOb, gl, gb, N, bad);
-        whiten<HC, N>(a.K_diag, C, EC, cvEc, gl, gb, 2 * N + 1, bad);
+        // each block is loaded and whitened in turn (its covariance data live
+        // only that long)
+        {
+            T cv[MM];
+            load_obs_raw<N, MM>(A, 0, cv, j, L, gl, CUR, 0, src, valid);
+            whiten<HA, MM>(a.C_diag, A, 0, cv, gl, gb, 0, bad);
+        }
+        {
+            T cv[N];
+            load_evol_raw<N>(A, RO, cv, j + 1, L, gl, CUR, RIGHT, 0, src, valid);
+            whiten<HA, N>(a.K_diag, A, RO, cv, gl, gb, 0, bad);
+        }
+        {
+            T cv[MM];
+            load_obs_raw<N, MM>(B, OB, cv, j + 1, L, gl, RIGHT, N, src, valid);
+            whiten<HB, MM>(a.C_diag, B, OB, cv, gl, gb, N, bad);
+        }
+        {
+            T cv[N];
+            load_evol_raw<N>(C, EC, cv, j, L, gl, LEFT, CUR, 2 * N + 1, src, valid && j >= 1);
+            whiten<HC, N>(a.K_diag, C, EC, cv, gl, gb, 2 * N + 1, bad);
+        }
     } else {
         const TIN *rec = slot<TIN>(src.sys_in, j - src.col0, GE::SREC);
         load_obs_sys<N>(A, 0, rec, L, CUR, valid);
@@ -552,6 +587,12 @@ __device__ __forceinline__ void fwd_unit(const FwdArgs &a, const FwdArgs &src, i
     for (int r = 0; r < N; ++r) Onew[r] = r < PB ? B[r] : T(0);
 
     if (INLINE_FOLD && fold) fold_part<N, MM, RAW, T, TIN>(a, src, t, gl, gb, L, Onew, dmin, dmax, bad, nonfinite);
+    if (keep && fold) {
+        // the caller folds the last column in (split fold) and stores the block
+#pragma unroll
+        for (int r = 0; r < N; ++r) keep[r] = Onew[r];
+        return;
+    }
 
     // reduced column t, observation block from step 3 (with the fold, if any)
     if (valid) {
@@ -610,6 +651,55 @@ __device__ __forceinline__ void reduce_slots(const double *slots, int64_t nprev,
 __device__ __forceinline__ void rank_flag(double dmin, double dmax, double tol, unsigned *flags) {
     if (threadIdx.x == 0 && !(dmin > tol * dmax))
         atomicOr(flags, FLAG_RANK);
+}
+
+// The units of block blk of a forward level.  With FOLD, the workgroup of
+// the last unit of an odd level also eliminates the last column: where a
+// wavefront after the last unit's is idle, that wavefront factors the last
+// column (fold_col) while the units run, and after one barrier the last unit
+// merges its Z rows (fold_merge); else the last unit does both in turn.
+template <int N, int MM, bool RAW, bool FOLD, class T, class TIN>
+__device__ __forceinline__ void fwd_level(const FwdArgs &a, const FwdArgs &src, int64_t blk, const Grp<N> &g,
+                                          double &dmin, double &dmax, bool &bad, bool &nonfinite) {
+    using GE = Geo<N>;
+    const int64_t t = blk * GE::UPB + g.ui;
+    if constexpr (!FOLD) {
+        fwd_unit<N, MM, RAW, false, T, TIN>(a, src, t, g.in, g.gl, g.gbase, dmin, dmax, bad, nonfinite);
+        return;
+    }
+    const int64_t tl = a.units - 1;
+    const bool fold_wg = (a.Nl & 1) && blk == tl / GE::UPB;  // uniform over the workgroup
+    const int wl = (int)(tl % GE::UPB) / GE::UPW;           // wavefront of the last unit
+    if (!(fold_wg && wl + 1 < kBlock / 64)) {
+        fwd_unit<N, MM, RAW, FOLD, T, TIN>(a, src, t, g.in, g.gl, g.gbase, dmin, dmax, bad, nonfinite);
+        return;
+    }
+    __shared__ T zb[N * (N + 1)];  // Z | zeta of the last column, row-major
+    T keep[N];
+    fwd_unit<N, MM, RAW, false, T, TIN>(a, src, t, g.in, g.gl, g.gbase, dmin, dmax, bad, nonfinite, -1, keep);
+    const LaneRole<N> L(g.gl);
+    if (g.in && g.ui == (wl + 1) * GE::UPW) {  // first unit slot of the next (idle) wavefront
+        T C2[2 * N];
+        fold_col<N, MM, RAW, T, TIN>(a, src, tl, g.gl, g.gbase, L, C2, dmin, dmax, bad, nonfinite);
+        const int c = L.role == LEFT ? L.rc : (L.role == RHS ? N : -1);
+        if (c >= 0) {
+#pragma unroll
+            for (int r = 0; r < N; ++r) zb[r * (N + 1) + c] = C2[N + r];
+        }
+    }
+    __syncthreads();
+    if (g.in && t == tl) {
+        const int c = L.role == RIGHT ? L.rc : (L.role == RHS ? N : -1);
+        T z[N];
+#pragma unroll
+        for (int r = 0; r < N; ++r) z[r] = c >= 0 ? zb[r * (N + 1) + c] : T(0);
+        fold_merge<N, T>(keep, z, g.gl, g.gbase);
+        if (c >= 0) {
+            T *rec = slot<T>(a.sys_out, tl, GE::SREC);
+#pragma unroll
+            for (int r = 0; r < N; ++r) rec[r * (N + 1) + c] = keep[r];
+        }
+    }
 }
 
 // Staging of a workgroup's inputs in LDS.  The workgroup's units read
@@ -691,18 +781,21 @@ template <int N, int MM, bool RAW, class T, class TIN, bool BATCH, bool FOLD = f
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(wf_min_waves(N)))) void k_forward(
     FwdArgs a0, const FwdArgs *tab, BlockMap bm) {
     const FwdArgs &a = BATCH ? tab[bm.item[blockIdx.x]] : a0;
-    const int64_t blk = BATCH ? bm.blk[blockIdx.x] : (int64_t)blockIdx.x;
+    // with FOLD the workgroup holding the last unit (which also folds the
+    // last column in, the longest chain of the launch) is dispatched first
+    const int64_t blk = BATCH  ? bm.blk[blockIdx.x]
+                        : FOLD ? (int64_t)(gridDim.x - 1 - blockIdx.x)
+                               : (int64_t)blockIdx.x;
     const Grp<N> g;
     bool bad = false, nonfinite = false;
     double dmin = INFINITY, dmax = 0.0;
-    const int64_t t = blk * Geo<N>::UPB + g.ui;
     if constexpr (STG && Stage<N, MM, RAW>::ON) {
         __shared__ double lds[Stage<N, MM, RAW>::WORDS];
         FwdArgs v = a;
         stage_inputs<N, MM, RAW, TIN>(a, blk, lds, v);
-        fwd_unit<N, MM, RAW, FOLD, T, TIN>(a, v, t, g.in, g.gl, g.gbase, dmin, dmax, bad, nonfinite);
+        fwd_level<N, MM, RAW, FOLD, T, TIN>(a, v, blk, g, dmin, dmax, bad, nonfinite);
     } else {
-        fwd_unit<N, MM, RAW, FOLD, T, TIN>(a, a, t, g.in, g.gl, g.gbase, dmin, dmax, bad, nonfinite);
+        fwd_level<N, MM, RAW, FOLD, T, TIN>(a, a, blk, g, dmin, dmax, bad, nonfinite);
     }
     block_minmax<kBlock>(dmin, dmax, bad, nonfinite, a.flags);
     if (threadIdx.x == 0) {
@@ -1076,6 +1169,13 @@ static void launch_fwd_t(const FwdArgs &a, hipStream_t s) {
                        0, s, a, nullptr, BlockMap{});
 }
 
+template <int N, int MM, class T, bool STG = true>
+static void launch_fwd_fold_raw_t(const FwdArgs &a, hipStream_t s) {
+    const int64_t blocks = (a.units + Geo<N>::UPB - 1) / Geo<N>::UPB;
+    hipLaunchKernelGGL((k_forward<N, MM, true, T, double, false, true, STG>), dim3((unsigned)blocks), dim3(kBlock),
+                       0, s, a, nullptr, BlockMap{});
+}
+
 template <int N, int MM, class T, class TIN>
 static void launch_fwd_fold_t(const FwdArgs &a, hipStream_t s) {
     const int64_t blocks = (a.units + Geo<N>::UPB - 1) / Geo<N>::UPB;
@@ -1191,6 +1291,8 @@ constexpr KernelSet make_set_base() {
 template <int N, int MM>
 constexpr KernelSet make_set() {
     KernelSet s = make_set_base<N, MM>();
+    s.fwd_fold_raw[0] = &launch_fwd_fold_raw_t<N, MM, double>;
+    s.fwd_fold_raw[1] = &launch_fwd_fold_raw_t<N, MM, float>;
     s.fwd_multi_raw[0] = &launch_fwd_multi_t<N, MM, true, double, double>;
     s.fwd_multi_raw[1] = &launch_fwd_multi_t<N, MM, true, float, double>;
     s.fwd_multi[FV_F64] = &launch_fwd_multi_t<N, MM, false, double, double>;
@@ -1209,6 +1311,8 @@ constexpr KernelSet make_set_unstaged() {
     s.fwd_raw[1] = &launch_fwd_t<N, MM, true, float, double, false>;
     s.fwd_raw_b[0] = &launch_fwd_bt<N, MM, true, double, double, false>;
     s.fwd_raw_b[1] = &launch_fwd_bt<N, MM, true, float, double, false>;
+    s.fwd_fold_raw[0] = &launch_fwd_fold_raw_t<N, MM, double, false>;
+    s.fwd_fold_raw[1] = &launch_fwd_fold_raw_t<N, MM, float, false>;
     s.fv = 1;
     return s;
 }

@@ -607,7 +607,10 @@ template <int N, int MM, bool RAW, class T, class TIN, bool BATCH, bool FOLD = f
 __global__ __launch_bounds__(WThreads<N>::NT) __attribute__((amdgpu_waves_per_eu(wg_min_waves(N)))) void k_wg_forward(FwdArgs a0, const FwdArgs *tab,
                                                                     BlockMap bm) {
     const FwdArgs &a = BATCH ? tab[bm.item[blockIdx.x]] : a0;
-    const int64_t blk = BATCH ? bm.blk[blockIdx.x] : (int64_t)blockIdx.x;
+    // with FOLD the last unit (which also folds, the longest chain) is dispatched first
+    const int64_t blk = BATCH  ? bm.blk[blockIdx.x]
+                        : FOLD ? (int64_t)(gridDim.x - 1 - blockIdx.x)
+                               : (int64_t)blockIdx.x;
     __shared__ T vbuf[4 * WGeo<N, T>::VB];
     bool bad = false, nonfinite = false;
     double dmin = INFINITY, dmax = 0.0;

@@ -95,6 +95,9 @@ const KernelSet *find_kernels(int n, int m, int fv, int bv) {
     s.upb_fwd = f->upb_fwd;
     s.upb_fwd_tail = f->upb_fwd_tail;
     std::memcpy(s.fwd_fold, f->fwd_fold, sizeof(s.fwd_fold));
+    std::memcpy(s.fwd_fold_raw, f->fwd_fold_raw, sizeof(s.fwd_fold_raw));
+    s.raw_diag_only = f->raw_diag_only;
+    s.narrow_units = f->narrow_units;
     std::memcpy(s.fwd_multi_raw, f->fwd_multi_raw, sizeof(s.fwd_multi_raw));
     std::memcpy(s.fwd_multi, f->fwd_multi, sizeof(s.fwd_multi));
     s.upb_multi = f->upb_multi;

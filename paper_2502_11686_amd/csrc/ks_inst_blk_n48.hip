@@ -1,5 +1,5 @@
 // ks_inst_blk_n48.hip -- workgroup-family kernel instantiations for n = 48.
-#include "ks_device_blk.h"
+#include "ks_device_mf.h"
 
 namespace ks {
 
@@ -7,6 +7,7 @@ namespace ks {
 const KernelSetList &list_blk_n48() {
     static const KernelSet sets[] = {
     KS_BLK_SETS_ONE(48),  // two records per workgroup would exceed the LDS
+    KS_MF_SETS(48),       // forward variant 1: MFMA forward
     };
     static const KernelSetList list = {sets, sizeof(sets) / sizeof(sets[0])};
     return list;

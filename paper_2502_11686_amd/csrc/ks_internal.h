@@ -98,7 +98,7 @@ enum BwdMode { BWD_Y = 0, BWD_COV = 1, BWD_BOTH = 2 };
 
 // precision variant of a forward launch: compute/storage type and the type of
 // the records it reads
-enum FwdVariant { FV_F64 = 0, FV_F32 = 1, FV_F64_FROM_F32 = 2 };
+enum FwdVariant { FV_F64 = 0, FV_F32 = 1, FV_F64_FROM_F32 = 2, FV_F64_NARROW = 3, kFwdVariants = 4 };
 
 using FwdFn = void (*)(const FwdArgs &, hipStream_t);
 using BwdFn = void (*)(const BwdArgs &, hipStream_t);
@@ -121,18 +121,18 @@ using TailBFn = void (*)(const FwdTailArgs *, BlockMap, int64_t blocks, hipStrea
 struct KernelSet {
     int n, mm;
     FwdFn fwd_raw[2];       // level 0 from the FP64 inputs: [FP64 | FP32]
-    FwdFn fwd[3];           // levels >= 1, indexed by FwdVariant
+    FwdFn fwd[kFwdVariants];  // levels >= 1, indexed by FwdVariant
     FwdFn fold_raw[2];      // last column of an odd level
-    FwdFn fold[3];
+    FwdFn fold[kFwdVariants];
     TailFn fwd_tail_raw;    // single-workgroup tail starting at level 0 (FP64)
     TailFn fwd_tail;        // tail starting above level 0 (FP64 records in and out)
     BwdFn bwd[3][2];        // [BwdMode][records FP64 | FP32]; arithmetic in FP64
     BwdFn bwd_tail[3];      // FP64 records
     // the same kernels driven by work tables (one launch for many problems)
     FwdBFn fwd_raw_b[2];
-    FwdBFn fwd_b[3];
+    FwdBFn fwd_b[kFwdVariants];
     FwdBFn fold_raw_b[2];
-    FwdBFn fold_b[3];
+    FwdBFn fold_b[kFwdVariants];
     TailBFn fwd_tail_raw_b;
     TailBFn fwd_tail_b;
     BwdBFn bwd_b[3][2];
@@ -143,7 +143,7 @@ struct KernelSet {
     int upb_bwd_tail[3];
     // levels >= 1 with the odd level's fold done by the level kernel's last
     // unit (no separate fold launch); null where the family has none
-    FwdFn fwd_fold[3];
+    FwdFn fwd_fold[kFwdVariants];
     // groups of consecutive levels in one launch (subtree fusion), null where
     // the family has none: forward groups starting at level 0 ([FP64 | FP32])
     // and above it (indexed by the FwdVariant of the group's first level);
@@ -151,14 +151,34 @@ struct KernelSet {
     // the records of columns i with c 2^(level+1) < i+1 < (c+1) 2^(level+1)),
     // [BwdMode][records FP64 | FP32]
     FwdMFn fwd_multi_raw[2];
-    FwdMFn fwd_multi[3];
+    FwdMFn fwd_multi[kFwdVariants];
     BwdFn bwd_multi[3][2];
     int upb_multi;    // units per pass of a forward group workgroup
     int rpp_multi;    // records per pass of a backward group workgroup
     // which compiled variant of the (n, observation class) this set is: its
     // forward half (fv) and backward half (bv); 0 = the default of n
     int fv, bv;
+    // level 0 of an odd-N_0 problem with the last column folded in by the
+    // level kernel ([FP64 | FP32]); null where the family has none
+    FwdFn fwd_fold_raw[2];
+    // nonzero: the level-0 forward whitens diagonal covariances only, so
+    // problems with a dense covariance take forward variant 0 instead
+    int raw_diag_only;
+    // nonzero: FP64 levels >= 1 with fewer units than this run the kernels
+    // of FV_F64_NARROW (a family whose units finish sooner, for levels too
+    // narrow to fill the device)
+    int narrow_units;
 };
+
+// The forward variant of level l: FP32 below the FP32-form switch l_switch,
+// FP64 reading FP32 records at it, FP64 above; FP64 levels >= 1 narrower
+// than the set's narrow_units take FV_F64_NARROW.  The same for a plan, a
+// batch and the engine, so a problem's kernels never depend on its company.
+inline int level_variant(const KernelSet *k, int l, int l_switch, int64_t Nl) {
+    const int v = l < l_switch ? FV_F32 : (l == l_switch && l > 0 ? FV_F64_FROM_F32 : FV_F64);
+    if (v == FV_F64 && l >= 1 && k->narrow_units > 0 && Nl / 2 < k->narrow_units) return FV_F64_NARROW;
+    return v;
+}
 
 struct KernelSetList {
     const KernelSet *sets;

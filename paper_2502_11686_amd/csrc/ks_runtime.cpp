@@ -317,6 +317,9 @@ Tuning tuning_for(int n, int precision) {
 const ks::KernelSet *tuned_kernels(const ks_desc &d) {
     const Tuning tu = tuning_for(d.n, d.precision);
     const ks::KernelSet *k = ks::find_kernels(d.n, d.m, tu.fwd_variant, tu.bwd_variant);
+    // a forward variant that whitens diagonal covariances only stands back for dense ones
+    if (k && k->raw_diag_only && (d.K_layout != KS_COV_DIAG || d.C_layout != KS_COV_DIAG))
+        k = ks::find_kernels(d.n, d.m, 0, tu.bwd_variant);
     return k ? k : ks::find_kernels(d.n, d.m);
 }
 
@@ -405,7 +408,7 @@ void enqueue_forward(ks_plan *p, const double *H, const double *F, const double 
         const int64_t blocks = (a.units + p->kset->upb_fwd - 1) / p->kset->upb_fwd;
         a.fold_slot = a.slots + 2 * blocks;
         // precision of this level: FP32 below the switch, FP64 from it on
-        const int v = l < ls ? ks::FV_F32 : (l == ls && l > 0 ? ks::FV_F64_FROM_F32 : ks::FV_F64);
+        const int v = ks::level_variant(p->kset, l, ls, lo.Nl[l]);
         if (end - l >= 2) {
             // levels l .. end-1 in one launch: each workgroup an aligned subtree
             ks::FwdMultiArgs ma{};
@@ -427,11 +430,17 @@ void enqueue_forward(ks_plan *p, const double *H, const double *F, const double 
             (l == 0 ? p->kset->fwd_multi_raw[v == ks::FV_F32] : p->kset->fwd_multi[v])(ma, p->stream);
             if (l == 0) mark(p, KS_TIME_FWD_LEVEL0, 1);
         } else if (l == 0) {
-            // the level-0 bracket holds the level kernel alone (not the fold)
+            const int f32 = v == ks::FV_F32;
             mark(p, KS_TIME_FWD_LEVEL0, 0);
-            p->kset->fwd_raw[v == ks::FV_F32](a, p->stream);
-            mark(p, KS_TIME_FWD_LEVEL0, 1);
-            if (lo.Nl[l] & 1) p->kset->fold_raw[v == ks::FV_F32](a, p->stream);
+            if ((lo.Nl[l] & 1) && p->kset->fwd_fold_raw[f32]) {
+                p->kset->fwd_fold_raw[f32](a, p->stream);  // the level kernel folds the last column itself
+                mark(p, KS_TIME_FWD_LEVEL0, 1);
+            } else {
+                // the level-0 bracket holds the level kernel alone (not the fold)
+                p->kset->fwd_raw[f32](a, p->stream);
+                mark(p, KS_TIME_FWD_LEVEL0, 1);
+                if (lo.Nl[l] & 1) p->kset->fold_raw[f32](a, p->stream);
+            }
         } else if ((lo.Nl[l] & 1) && p->kset->fwd_fold[v]) {
             p->kset->fwd_fold[v](a, p->stream);  // the level kernel folds the last column itself
         } else {
@@ -977,13 +986,12 @@ void plan_batch(ks_batch *b) {
         const int mode = cov ? ks::BWD_BOTH : ks::BWD_Y;
         for (int s = 0; s < maxL0; ++s) {
             for (auto *cls : classes) {
-                for (int v = 0; v < 3; ++v) {
+                for (int v = 0; v < ks::kFwdVariants; ++v) {
                     BLaunch fl{BLaunch::FWD, cls, v, s == 0, (int64_t)b->map_item.size(), 0};
                     for (int i = 0; i < P; ++i) {
                         const BatchProblem &pr = b->probs[i];
                         if (pr.kset != cls || s >= pr.l0) continue;
-                        const int vi = s < pr.l_switch ? ks::FV_F32
-                                     : (s == pr.l_switch && s > 0 ? ks::FV_F64_FROM_F32 : ks::FV_F64);
+                        const int vi = ks::level_variant(pr.kset, s, pr.l_switch, pr.lo.Nl[s]);
                         if (vi != v) continue;
                         const int64_t units = pr.lo.Nl[s] / 2;
                         const int64_t blocks = (units + cls->upb_fwd - 1) / cls->upb_fwd;
@@ -995,8 +1003,7 @@ void plan_batch(ks_batch *b) {
                     for (int i = 0; i < P; ++i) {
                         const BatchProblem &pr = b->probs[i];
                         if (pr.kset != cls || s >= pr.l0 || !(pr.lo.Nl[s] & 1)) continue;
-                        const int vi = s < pr.l_switch ? ks::FV_F32
-                                     : (s == pr.l_switch && s > 0 ? ks::FV_F64_FROM_F32 : ks::FV_F64);
+                        const int vi = ks::level_variant(pr.kset, s, pr.l_switch, pr.lo.Nl[s]);
                         if (vi != v) continue;
                         add_map(fwd_index[i][s], 0, s);
                         fo.blocks += 1;
@@ -1422,9 +1429,7 @@ void eng_free(ks_engine *e, size_t off, size_t bytes) {
     }
 }
 
-int fwd_variant(const BatchProblem &pr, int s) {
-    return s < pr.l_switch ? ks::FV_F32 : (s == pr.l_switch && s > 0 ? ks::FV_F64_FROM_F32 : ks::FV_F64);
-}
+int fwd_variant(const BatchProblem &pr, int s) { return ks::level_variant(pr.kset, s, pr.l_switch, pr.lo.Nl[s]); }
 
 int64_t fwd_blocks(const BatchProblem &pr, int l) {
     return (pr.lo.Nl[l] / 2 + pr.kset->upb_fwd - 1) / pr.kset->upb_fwd;
@@ -1705,7 +1710,7 @@ ks_status ks_engine_step(ks_engine *e, int32_t *finished) {
     // launch list; a request's fold follows its level's launch
     for (auto *cls : classes) {
         for (int raw = 1; raw >= 0; --raw)
-            for (int v = 0; v < 3; ++v) {
+            for (int v = 0; v < ks::kFwdVariants; ++v) {
                 BLaunch fl{BLaunch::FWD, cls, v, raw == 1, (int64_t)item.size(), 0};
                 std::vector<size_t> folds;
                 for (size_t q = 0; q < R; ++q) {
