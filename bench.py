@@ -256,6 +256,11 @@ def large_block_leg(check: bool, dev):
         plan.close()
         avg_s = ms / max(cnt, 1) / 1e3
         peak = FP32_VALU_PEAK_TFS if level0_fp32 else FP64_VALU_PEAK_TFS
+        # FP64 level 0 of forward variant 1 (diagonal covariances): the blocked
+        # QR whose trailing updates run on the FP64 matrix cores (their dense
+        # peak equals the FP64 vector peak, 78.6 TFLOP/s)
+        on_mfma = (not level0_fp32 and p.K_diag and p.C_diag
+                   and ks.get_tuning(p.n, False)["fwd_variant"] == 1 and ks.kernel_variants(p.n, p.m, False) >= 2)
         algo = level0_forward_bytes(p, 4 if level0_fp32 else 8)
         err = None
         if ref is not None:
@@ -268,9 +273,10 @@ def large_block_leg(check: bool, dev):
             "value": (p.k + 1) * steps / el, "unit": "steps/s", "ms_per_step": el / steps * 1e3,
             "err_vs_oracle": err,
             "pass_model_tflops": model_flops / (el / steps) / 1e12,
-            "roofline": {"bound": "alu", "achieved": flops / avg_s / 1e12, "peak": peak, "unit": "TFLOP/s",
-                         "frac": flops / avg_s / 1e12 / peak, "traffic": None,
-                         "kernel": f"level-0 forward (n={p.n}, m={p.m}, {'FP32' if level0_fp32 else 'FP64'})",
+            "roofline": {"bound": "mfma" if on_mfma else "alu", "achieved": flops / avg_s / 1e12, "peak": peak,
+                         "unit": "TFLOP/s", "frac": flops / avg_s / 1e12 / peak, "traffic": None,
+                         "kernel": f"level-0 forward (n={p.n}, m={p.m}, {'FP32' if level0_fp32 else 'FP64'}"
+                                   f"{', blocked QR on FP64 matrix cores' if on_mfma else ''})",
                          "algo_flops_per_launch": flops, "algo_bytes_per_launch": algo,
                          "avg_launch_ms": avg_s * 1e3, "launches_timed": cnt,
                          "hbm_frac": algo / avg_s / 1e9 / HBM_PEAK_GBS}}

@@ -230,7 +230,10 @@ ks_status ks_kernel_time(const ks_plan *plan, double *total_ms, int64_t *count);
  * form.  None of them changes what is computed: with the same kernel
  * variants every unit and block row does the same arithmetic whichever
  * launch runs it, so FP64 results are bitwise independent of the tail passes
- * and level groups (the FP32 switch changes which levels run in FP32, hence
+ * and level groups (a level that runs the matrix-core forward of forward
+ * variant 1, n = 32, 48, always has a launch of its own, so the tail, which
+ * has the arithmetic of the narrow-level kernels, never takes it over; the
+ * FP32 switch changes which levels run in FP32, hence
  * FP32-form results; another kernel variant is another compiled kernel and
  * may round differently).  Plans, batches and the engine read the same
  * table, so a problem's results are the same through all three.

@@ -339,6 +339,16 @@ Schedule make_schedule(const ks_desc &d, const ks::KernelSet *kset, const Layout
         while (sc.l_switch < lo.L && lo.Nl[sc.l_switch] > tu.switch_cols) ++sc.l_switch;
     int l0 = tail_start(lo, kset->upb_fwd_tail, tu.fwd_passes, false);
     if (sc.l_switch > 0 && l0 <= sc.l_switch) l0 = sc.l_switch + 1;  // the tail reads FP64 records only
+    if (kset->narrow_units > 0) {
+        // the tail kernels do the arithmetic of the narrow-level kernels, so a
+        // level whose own launch would run the wide-level forward stays out of
+        // the tail: the tail passes never change results
+        for (int l = 0; l <= lo.L; ++l) {
+            const bool wide = l == 0 ? sc.l_switch == 0
+                                     : ks::level_variant(kset, l, sc.l_switch, lo.Nl[l]) == ks::FV_F64;
+            if (wide && l0 <= l) l0 = l + 1;
+        }
+    }
     sc.l0 = l0 > lo.L ? lo.L : l0;                                    // the base always runs in the tail
     int l1 = tail_start(lo, kset->upb_bwd_tail[bwd_mode], tu.bwd_passes, true);
     sc.l1 = l1 < sc.l_switch ? sc.l_switch : l1;

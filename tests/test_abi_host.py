@@ -227,3 +227,18 @@ def test_static_entry_rejects_oversized_and_invalid_problems():
     bad = ks.make_desc(1000, 7, 3, False, False)  # no kernels for n = 7
     assert L.ks_smooth_cov_static(ctypes.byref(bad), *([fake] * 9), None) == ks.KS_E_ARG
     assert L.ks_smooth_cov_static(None, *([fake] * 9), None) == ks.KS_E_ARG
+
+
+def test_matrix_core_levels_stay_out_of_the_forward_tail(monkeypatch):
+    """Forward variant 1 of n = 48 with diagonal covariances: however many
+    tail passes are allowed, the levels that run the matrix-core forward
+    (level 0 and the levels of at least 512 units) keep launches of their own,
+    since the tail has the arithmetic of the narrow-level kernels."""
+    monkeypatch.setenv("KS_FWD_VARIANT", "1")
+    monkeypatch.setenv("KS_TAIL_PASSES", "1000000")
+    k = 20000
+    first_narrow = next(l for l in range(1, 20) if ((k + 1) >> l) // 2 < 512)
+    assert _fake_plan(k, 48, 24)[1] == first_narrow
+    assert _fake_plan(300, 48, 24)[1] == 1  # every level >= 1 narrow: only level 0 stays out
+    monkeypatch.setenv("KS_FWD_VARIANT", "0")
+    assert _fake_plan(k, 48, 24)[1] == 0  # the default family: everything may go to the tail

@@ -50,7 +50,11 @@ def test_fp32_form_small_switch(n, m, cov, switch, monkeypatch):
     print(f"n={n} switch={switch}: state {eu:.2e} cov {es:.2e}", flush=True)
     assert eu < TOL and es < TOL
     assert np.array_equal(S, np.swapaxes(S, 1, 2))
-    # no FP32 level at all: identical to the FP64 path
+    # no FP32 level at all: identical to the FP64 path run with the same
+    # kernel variants (the tuning table may pick other variants per form)
+    t = ks.get_tuning(n, False)
+    monkeypatch.setenv("KS_FWD_VARIANT", str(t["fwd_variant"]))
+    monkeypatch.setenv("KS_BWD_VARIANT", str(t["bwd_variant"]))
     u64, S64 = run(p, False, monkeypatch, None)
     u32, S32 = run(p, True, monkeypatch, 10 ** 9)
     assert np.array_equal(u64, u32) and np.array_equal(S64, S32)
