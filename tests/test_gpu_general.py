@@ -21,14 +21,17 @@ def test_general_dimensions_match_dense_definition(seed, k, n_choices, m_extra, 
     res = general.smooth_general(gp, fp32=fp32)
     torch.cuda.synchronize()
     ref = dense.smooth_general(gp)
-    tol = 1e-5 if fp32 else 1e-9
+    # the FP64 gates of the uniform problems (states 1e-10 normwise, covariance
+    # blocks 1e-9); the dense definition itself agrees with the sequential
+    # oracle on these embedded problems to 6e-13
+    tol_u, tol_s = (1e-5, 1e-5) if fp32 else (1e-10, 1e-9)
     scale = max(np.abs(x).max() for x in ref["u"])
     for i in range(gp.k + 1):
         u = res.u(i).cpu().numpy()
         S = res.cov(i).cpu().numpy()
-        assert np.abs(u - ref["u"][i]).max() <= tol * scale, i
-        assert np.linalg.norm(S - ref["cov"][i]) <= tol * np.linalg.norm(ref["cov"][i]), i
+        assert np.abs(u - ref["u"][i]).max() <= tol_u * scale, i
+        assert np.linalg.norm(S - ref["cov"][i]) <= tol_s * np.linalg.norm(ref["cov"][i]), i
     for i in range(gp.k):
         L1 = res.lag1(i).cpu().numpy()
         den = np.sqrt(np.linalg.norm(ref["cov"][i]) * np.linalg.norm(ref["cov"][i + 1]))
-        assert np.linalg.norm(L1 - ref["lag1"][i]) <= tol * den, i
+        assert np.linalg.norm(L1 - ref["lag1"][i]) <= tol_s * den, i

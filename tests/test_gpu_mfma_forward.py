@@ -102,3 +102,15 @@ def test_batch_equals_alone_with_variant_1(variant1):
             assert np.array_equal(u.cpu().numpy(), ua) and np.array_equal(S.cpu().numpy(), Sa), (p.n, p.k)
     finally:
         b.close()
+
+
+def test_fp32_form_with_a_wide_fp64_level(monkeypatch):
+    """The FP32 form where the first FP64 level above the switch level has at
+    least 512 units (k = 8200, switch 4096: levels 0, 1 in FP32, level 2 reads
+    FP32 records, level 3 with 512 units runs the matrix-core forward)."""
+    monkeypatch.setenv("KS_FWD_VARIANT", "1")
+    monkeypatch.setenv("KS_FP32_SWITCH", "4096")
+    p = gen.make_problem(np.random.default_rng(44), 8200, 32, 16, cov="diag")
+    u, S = smooth(p, fp32=True)
+    eu, es = errs(u, S, seq.smooth(p))
+    assert eu < 1e-5 and es < 1e-5, (eu, es)
