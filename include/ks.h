@@ -284,7 +284,10 @@ ks_status ks_get_tuning(int32_t n, int32_t precision, ks_tuning *out);
  * FP64 matrix cores (blocked Householder QR, compact-WY updates; narrower
  * levels and the FP32-form levels keep the default kernels) and applies to
  * problems with diagonal K and C only -- a problem with a dense covariance
- * takes variant 0 instead; backward variants of the MFMA family take 4, 2 or
+ * takes variant 0 instead; forward variant 2 of n = 32, 48 is the default
+ * 2-D tiled forward compiled for another occupancy target (n = 32 without
+ * the four-wavefronts-per-SIMD register cap, n = 48 with it); backward
+ * variants of the MFMA family take 4, 2 or
  * 1 records per workgroup (n <= 12; n = 16, 24: 2 or 1; n = 32: 1 or 2), and
  * for n = 1, 2, 3, 5 backward variant 1 is the MFMA family instead of the
  * wavefront family.  Host-only. */

@@ -785,4 +785,28 @@ constexpr KernelSet make_mf_set() {
 }
 #define KS_MF_SETS(N) make_mf_set<N, wg_mm_small(N)>(), make_mf_set<N, N>()
 
+// Forward variant 2 of n = 32, 48: the 2-D tiled forward compiled for the
+// other occupancy target (wg_alt_waves); backward as in the default set.
+template <int N, int MM>
+constexpr KernelSet make_occ_set() {
+    constexpr int MW = wg_alt_waves(N);
+    KernelSet s = make_blk_set<N, MM, blk_rpw(N), 0>();
+    s.fwd_raw[0] = &launch_wg_fwd_t<N, MM, true, double, double, MW>;
+    s.fwd_raw[1] = &launch_wg_fwd_t<N, MM, true, float, double, MW>;
+    s.fwd[FV_F64] = &launch_wg_fwd_t<N, MM, false, double, double, MW>;
+    s.fwd[FV_F32] = &launch_wg_fwd_t<N, MM, false, float, float, MW>;
+    s.fwd[FV_F64_FROM_F32] = &launch_wg_fwd_t<N, MM, false, double, float, MW>;
+    s.fwd_raw_b[0] = &launch_wg_fwd_bt<N, MM, true, double, double, MW>;
+    s.fwd_raw_b[1] = &launch_wg_fwd_bt<N, MM, true, float, double, MW>;
+    s.fwd_b[FV_F64] = &launch_wg_fwd_bt<N, MM, false, double, double, MW>;
+    s.fwd_b[FV_F32] = &launch_wg_fwd_bt<N, MM, false, float, float, MW>;
+    s.fwd_b[FV_F64_FROM_F32] = &launch_wg_fwd_bt<N, MM, false, double, float, MW>;
+    s.fwd_fold[FV_F64] = &launch_wg_fwd_fold_t<N, MM, double, double, MW>;
+    s.fwd_fold[FV_F32] = &launch_wg_fwd_fold_t<N, MM, float, float, MW>;
+    s.fwd_fold[FV_F64_FROM_F32] = &launch_wg_fwd_fold_t<N, MM, double, float, MW>;
+    s.fv = 2;
+    return s;
+}
+#define KS_OCC_SETS(N) make_occ_set<N, wg_mm_small(N)>(), make_occ_set<N, N>()
+
 }  // namespace ks

@@ -36,6 +36,9 @@ constexpr int wg_tr(int n) { return n % 8 == 0 ? 8 : 4; }
 // SIMD fits and three workgroups share a CU.  n = 48 spills heavily under
 // the same constraint and runs unconstrained.
 constexpr int wg_min_waves(int n) { return n == 32 ? 4 : 1; }
+// the other target, compiled as forward variant 2 of n = 32, 48 (the
+// autotuner chooses): n = 32 unconstrained, n = 48 four wavefronts per SIMD
+constexpr int wg_alt_waves(int n) { return n == 32 ? 1 : 4; }
 constexpr int wg_mm_small(int n) { return ((n + 1) / 2 + 7) / 8 * 8; }
 
 template <int N, class T>
@@ -603,9 +606,10 @@ __device__ __forceinline__ void wg_fwd_unit(const FwdArgs &a, int64_t t, T *vbuf
 // With FOLD, the last unit of an odd level also folds the last column in
 // (its statistics join its workgroup's slot; the level's fold slot is set
 // neutral).
-template <int N, int MM, bool RAW, class T, class TIN, bool BATCH, bool FOLD = false>
-__global__ __launch_bounds__(WThreads<N>::NT) __attribute__((amdgpu_waves_per_eu(wg_min_waves(N)))) void k_wg_forward(FwdArgs a0, const FwdArgs *tab,
-                                                                    BlockMap bm) {
+// MW: the wavefronts per SIMD the kernel is compiled for (register budget).
+template <int N, int MM, bool RAW, class T, class TIN, bool BATCH, bool FOLD = false, int MW = wg_min_waves(N)>
+__global__ __launch_bounds__(WThreads<N>::NT) __attribute__((amdgpu_waves_per_eu(MW))) void k_wg_forward(
+    FwdArgs a0, const FwdArgs *tab, BlockMap bm) {
     const FwdArgs &a = BATCH ? tab[bm.item[blockIdx.x]] : a0;
     // with FOLD the last unit (which also folds, the longest chain) is dispatched first
     const int64_t blk = BATCH  ? bm.blk[blockIdx.x]
@@ -710,19 +714,19 @@ __global__ __launch_bounds__(WThreads<N>::NT) void k_wg_fwd_tail(FwdTailArgs ta0
     rank_flag(dmin, dmax, ta.rank_tol, ta.a.flags);
 }
 
-template <int N, int MM, bool RAW, class T, class TIN>
+template <int N, int MM, bool RAW, class T, class TIN, int MW = wg_min_waves(N)>
 static void launch_wg_fwd_t(const FwdArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((k_wg_forward<N, MM, RAW, T, TIN, false>), dim3((unsigned)a.units),
+    hipLaunchKernelGGL((k_wg_forward<N, MM, RAW, T, TIN, false, false, MW>), dim3((unsigned)a.units),
                        dim3(WGeo<N, double>::NT), 0, s, a, nullptr, BlockMap{});
 }
-template <int N, int MM, class T, class TIN>
+template <int N, int MM, class T, class TIN, int MW = wg_min_waves(N)>
 static void launch_wg_fwd_fold_t(const FwdArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((k_wg_forward<N, MM, false, T, TIN, false, true>), dim3((unsigned)a.units),
+    hipLaunchKernelGGL((k_wg_forward<N, MM, false, T, TIN, false, true, MW>), dim3((unsigned)a.units),
                        dim3(WGeo<N, double>::NT), 0, s, a, nullptr, BlockMap{});
 }
-template <int N, int MM, bool RAW, class T, class TIN>
+template <int N, int MM, bool RAW, class T, class TIN, int MW = wg_min_waves(N)>
 static void launch_wg_fwd_bt(const FwdArgs *tab, BlockMap bm, int64_t blocks, hipStream_t s) {
-    hipLaunchKernelGGL((k_wg_forward<N, MM, RAW, T, TIN, true>), dim3((unsigned)blocks),
+    hipLaunchKernelGGL((k_wg_forward<N, MM, RAW, T, TIN, true, false, MW>), dim3((unsigned)blocks),
                        dim3(WGeo<N, double>::NT), 0, s, FwdArgs{}, tab, bm);
 }
 template <int N, int MM, bool RAW, class T, class TIN>

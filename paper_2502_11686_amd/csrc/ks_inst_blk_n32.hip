@@ -8,6 +8,7 @@ const KernelSetList &list_blk_n32() {
     static const KernelSet sets[] = {
     KS_BLK_SETS(32),
     KS_MF_SETS(32),  // forward variant 1: MFMA forward
+    KS_OCC_SETS(32),  // forward variant 2: 2-D tiled forward at the other occupancy target
     };
     static const KernelSetList list = {sets, sizeof(sets) / sizeof(sets[0])};
     return list;
