@@ -155,9 +155,11 @@ __device__ __forceinline__ int mf_vidx(int i, int row) {
 // is zero.  Every lane applies it to its own column; the pivot column itself
 // becomes (.., beta, ~0, ..) and columns left of the pivot change only below
 // their diagonal, which no later step reads as R.
+// sum of squares of this lane's column over rows 16P + I + 1 .. 16R - 1, over
+// the four lanes of the column (four partial sums: short dependency chains)
 template <int RM, int R, int P, int OFF>
-__device__ __forceinline__ void mf_pivot(mf4 (&x)[RM], int I, double *vl, double *tau_lds, int c, int q) {
-    double s4[4] = {0.0, 0.0, 0.0, 0.0};  // four partial sums: short dependency chains
+__device__ __forceinline__ double mf_below(const mf4 (&x)[RM], int I, int q) {
+    double s4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int rt = P; rt < R; ++rt)
 #pragma unroll
@@ -165,7 +167,15 @@ __device__ __forceinline__ void mf_pivot(mf4 (&x)[RM], int I, double *vl, double
             const double v = x[OFF + rt][e];
             s4[e] = (rt > P || 4 * e + q > I) ? fma(v, v, s4[e]) : s4[e];
         }
-    const double xn2 = mf_readlane(mf_colsum((s4[0] + s4[1]) + (s4[2] + s4[3])), I);
+    return mf_colsum((s4[0] + s4[1]) + (s4[2] + s4[3]));
+}
+
+// ss: mf_below for pivot I on entry, for pivot I + 1 on return (formed right
+// after the update that fixes column I + 1, so the next pivot starts from it)
+template <int RM, int R, int P, int OFF>
+__device__ __forceinline__ void mf_pivot(mf4 (&x)[RM], int I, double &ss, double *vl, double *tau_lds, int c,
+                                         int q) {
+    const double xn2 = mf_readlane(ss, I);
     const int ei = I >> 2;
     const double xa = ei == 0 ? x[OFF + P][0] : ei == 1 ? x[OFF + P][1] : ei == 2 ? x[OFF + P][2] : x[OFF + P][3];
     const double alpha = mf_readlane(xa, ((I & 3) << 4) | I);
@@ -199,6 +209,7 @@ __device__ __forceinline__ void mf_pivot(mf4 (&x)[RM], int I, double *vl, double
 #pragma unroll
         for (int e = 0; e < 4; ++e) x[OFF + rt][e] = fma(-w, vi[rt * 4 + e], x[OFF + rt][e]);
     if (c == 0 && q == 0) tau_lds[I] = tau;
+    ss = mf_below<RM, R, P, OFF>(x, I + 1, q);
 }
 
 // Factor panel P (this wavefront's column tile: row tiles OFF + [0, R) of x):
@@ -208,8 +219,9 @@ __device__ __forceinline__ void mf_pivot(mf4 (&x)[RM], int I, double *vl, double
 template <int RM, int R, int P, int OFF = 0>
 __device__ __forceinline__ void mf_factor(mf4 (&x)[RM], double *vl, double *tb, double *gb, double *tau_lds,
                                           int c, int q) {
+    double ss = mf_below<RM, R, P, OFF>(x, 0, q);
 #pragma unroll 1
-    for (int i = 0; i < 16; ++i) mf_pivot<RM, R, P, OFF>(x, i, vl, tau_lds, c, q);
+    for (int i = 0; i < 16; ++i) mf_pivot<RM, R, P, OFF>(x, i, ss, vl, tau_lds, c, q);
     mf4 gram = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int rt = P; rt < R; ++rt)
