@@ -9,6 +9,8 @@
 // kernel table of the family.
 #pragma once
 
+#include <type_traits>
+
 #include "ks_device_wg.h"
 
 namespace ks {
@@ -52,6 +54,36 @@ struct BSmem {
     static constexpr int PER = DO + 3 * N;           // 1 / R_ii(r, r), y_a, y_b
 };
 
+// From n = 24 on, a record runs in the blocked form (blk_bwd_unit_bf): one
+// wavefront forms R_ii^{-1} by substitution while another solves for the
+// state, T_I comes from an MFMA product with R_ii^{-1}, the neighbours'
+// covariance blocks pass through LDS one block at a time, and P stays in
+// registers between its two products.  A record then needs 76 KB of LDS at
+// n = 48 (151 KB in the form above), so two records share a CU.
+constexpr bool blk_bf(int n) { return n >= 24; }
+
+// LDS of one record in the blocked form (doubles): region 0 holds R_ii, then
+// the neighbour block in use (S_aa, S_ab, S_bb in turn), then S_ii; then
+// [R_i,b | rho | R_i,a] (later [T_b | . | T_a]), RI = R_ii^{-1} (covariances
+// only), and 1 / R_ii(r, r), y_a, y_b
+template <int N, bool COV>
+struct BFSmem {
+    static constexpr int LR = N + 1;
+    static constexpr int LT = 2 * N + 1;
+    static constexpr int TO = N * LR;
+    static constexpr int IO = TO + N * LT;
+    static constexpr int DO = IO + (COV ? N * LR : 0);
+    static constexpr int PER = DO + 3 * N;
+};
+
+template <int N, bool COV>
+constexpr int blk_per() { return blk_bf(N) ? BFSmem<N, COV>::PER : BSmem<N, COV>::PER; }
+
+// wavefronts per SIMD the backward kernel is compiled for: two for the blocked
+// form with covariances (its LDS admits two workgroups per CU), else one
+template <int N, bool COV>
+constexpr int blk_min_waves() { return (COV && blk_bf(N)) ? 2 : 1; }
+
 // Synchronization inside one record's work.  A record taken by one
 // wavefront (n <= 12) shares its LDS region with no other wavefront, and a
 // wavefront's LDS accesses complete in order: fences that keep the compiler
@@ -82,8 +114,8 @@ __device__ __forceinline__ void rec_sync() {
 // BGeo<N>::UT threads per record (the record's own LDS region sm); every
 // thread of the workgroup must call it the same number of times.
 template <int N, bool DO_Y, bool DO_COV, class TR, int RPW = blk_rpw(N)>
-__device__ __forceinline__ void blk_bwd_unit(const BwdArgs &a, int l, int64_t t, int64_t units,
-                                             bool store_s, double *sm) {
+__device__ __forceinline__ void blk_bwd_unit_lds(const BwdArgs &a, int l, int64_t t, int64_t units,
+                                                 bool store_s, double *sm) {
     using BG = BGeo<N, RPW>;
     using SM = BSmem<N, DO_COV>;
     constexpr int W = BG::W;
@@ -323,11 +355,348 @@ __device__ __forceinline__ void blk_bwd_unit(const BwdArgs &a, int l, int64_t t,
     rec_sync<WPU>();
 }
 
+__device__ __forceinline__ double blk_readlane(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)b, lane);
+    const long long hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double((hi << 32) | lo);
+}
+
+// One block row in the blocked form (n >= 24, two or more wavefronts per
+// record, n <= 64):
+//  1. wavefront 0: RI = R_ii^{-1} by column-oriented substitution (lane g
+//     holds column g); meanwhile the state y_i = R_ii^{-1} (rho_i - R_i,a y_a
+//     - R_i,b y_b) (a matrix-vector product, then one right-hand side by
+//     substitution with the pivot broadcast from its lane) on wavefront 1 --
+//     wavefront 0 when covariances are not wanted, which then skip every step
+//     below -- and the other wavefronts fetch S_aa, S_ab, S_bb.
+//  2. T_I = RI [R_i,a | R_i,b] on MFMA (RI upper triangular: K from 16 ti),
+//     written over the R part of the row.
+//  3. P^T = S_II T_I^T: wavefront ti owns row tile ti of S_ii and forms the
+//     column tiles (tk, ti) of P^T, with the operand S_II read from LDS in
+//     three passes (S_aa, then S_ab, then S_bb in region 0; each tile takes
+//     its K steps in increasing order across the passes).  Tile (tk, ti) in
+//     the MFMA result layout is, element e, the A operand of K step 4 tk + e
+//     of P T_I^T, so P goes from one product to the next in registers.
+//  4. S_ii row tile ti = RI RI^T + P T_I^T, symmetrized on the way out; -P
+//     gives the blocks S_i,a, S_i,b kept for lower levels (and the lag-one
+//     blocks at level 0).
+template <int N, bool DO_Y, bool DO_COV, class TR, int RPW>
+__device__ __forceinline__ void blk_bwd_unit_bf(const BwdArgs &a, int l, int64_t t, int64_t units,
+                                                bool store_s, double *sm) {
+    using BG = BGeo<N, RPW>;
+    using SM = BFSmem<N, DO_COV>;
+    constexpr int W = BG::W;
+    constexpr int LR = SM::LR, LT = SM::LT;
+    constexpr int NT = BG::UT;
+    constexpr int WPU = BG::WPU;
+    constexpr int TM = (N + 15) / 16;      // row tiles of S_ii, T_I; column tiles of P^T
+    constexpr int TC = (2 * N + 15) / 16;  // column tiles of T_I, row tiles of P^T
+    static_assert(WPU >= 2 && WPU >= TM && N <= 64 && N % 4 == 0, "blocked form: record shape");
+    double *Rd = sm;  // R_ii; then S_aa, S_ab, S_bb in turn; then S_ii
+    double *TT = sm + SM::TO;
+    double *RI = sm + SM::IO;
+    double *DI = sm + SM::DO;
+    const int g = threadIdx.x % NT;
+    const int wave = g >> 6, lane = g & 63;
+    const int lr = lane & 15, lk = lane >> 4;
+    const bool valid = t < units;
+    const int64_t i = ((2 * t + 1) << l) - 1;
+    const int64_t aa = i - ((int64_t)1 << l), bb = i + ((int64_t)1 << l);
+    const bool va = valid && aa >= 0, vb = valid && bb <= a.k;
+    const TR *rec = slot<TR>(a.rrows_all, a.rec_off[l] + t, BG::RREC);
+
+    // the R row: every load issued before the first LDS store
+    constexpr int RPL = (N * W + NT - 1) / NT;
+    double rv[RPL];
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) {
+        const int idx = g + NT * u;
+        rv[u] = (idx < N * W && valid) ? double(rec[idx]) : 0.0;
+    }
+    double ya = 0.0, yb = 0.0;  // neighbour states, element g
+    if (DO_Y && g < N) {
+        ya = va ? a.u_in[aa * N + g] : 0.0;
+        yb = vb ? a.u_in[bb * N + g] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < RPL; ++u) {
+        const int idx = g + NT * u;
+        if (idx < N * W) {
+            const int r = idx / W, c = idx - r * W;
+            const double v = valid ? rv[u] : (c == r ? 1.0 : 0.0);
+            if (c < N) Rd[r * LR + c] = v;
+            else TT[r * LT + (c - N)] = v;
+        }
+    }
+    if (DO_Y && g < N) {
+        DI[N + g] = ya;
+        DI[2 * N + g] = yb;
+    }
+    rec_sync<WPU>();
+    if (g < N) DI[g] = rcp_nr(Rd[g * LR + g]);
+    rec_sync<WPU>();
+
+    // the neighbour blocks, one slice per thread of wavefronts 1 .. WPU-1
+    constexpr int NTS = NT - 64;
+    constexpr int NQ = DO_COV ? (N * N + NTS - 1) / NTS : 1;
+    double q_aa[NQ], q_ab[NQ], q_bb[NQ];
+    const double *sab = nullptr;
+    bool trans = false;
+    if constexpr (DO_COV) {
+        if (va && vb) {
+            const int la = __builtin_ctzll((unsigned long long)(aa + 1));
+            if (la == l + 1) {
+                sab = a.spm + (rec_of(aa, a.rec_off) - a.spm_first) * 2 * N * N + N * N;
+            } else {
+                sab = a.spm + (rec_of(bb, a.rec_off) - a.spm_first) * 2 * N * N;
+                trans = true;
+            }
+        }
+    }
+    if (DO_COV && wave == 0) {
+        if (lane < N) {
+            double x[N];
+#pragma unroll
+            for (int r = 0; r < N; ++r) x[r] = r == lane ? 1.0 : 0.0;
+#pragma unroll
+            for (int r = N - 1; r >= 0; --r) {
+                const double xr = x[r] * DI[r];
+                x[r] = xr;
+#pragma unroll
+                for (int s = 0; s < r; ++s) x[s] = fma(-Rd[s * LR + r], xr, x[s]);
+            }
+#pragma unroll
+            for (int r = 0; r < N; ++r) RI[r * LR + lane] = x[r];
+        }
+    } else {
+        if constexpr (DO_COV) {
+#pragma unroll
+            for (int u = 0; u < NQ; ++u) {
+                const int idx = (g - 64) + NTS * u;
+                const bool in = idx < N * N;
+                q_aa[u] = (in && va) ? a.cov[aa * N * N + idx] : 0.0;
+                q_ab[u] = (in && sab) ? sab[idx] : 0.0;
+                q_bb[u] = (in && vb) ? a.cov[bb * N * N + idx] : 0.0;
+            }
+        }
+        if (DO_Y && wave == (DO_COV ? 1 : 0)) {
+            // w = rho - R_i,a y_a - R_i,b y_b (lane g: row g), then R_ii y = w
+            double w = 0.0;
+            if (lane < N) {
+                w = TT[lane * LT + N];
+#pragma unroll 8
+                for (int d = 0; d < N; ++d) {
+                    w = fma(-TT[lane * LT + N + 1 + d], DI[N + d], w);
+                    w = fma(-TT[lane * LT + d], DI[2 * N + d], w);
+                }
+            }
+            double yg = 0.0;
+#pragma unroll
+            for (int r = N - 1; r >= 0; --r) {
+                const double yr = blk_readlane(w, r) * DI[r];
+                if (lane == r) yg = yr;
+                if (lane < r) w = fma(-Rd[lane * LR + r], yr, w);
+            }
+            if (valid && lane < N) a.u_out[i * N + lane] = yg;
+        }
+    }
+    if constexpr (!DO_COV) {
+        rec_sync<WPU>();
+        return;
+    }
+    rec_sync<WPU>();  // RI complete; R_ii no longer read: region 0 takes S_aa
+
+    // T_I(r, d) = [T_a | T_b](r, d) in [T_b | . | T_a] (same place as the R part)
+    auto TX = [&](int r, int d) -> double { return d < N ? TT[r * LT + N + 1 + d] : TT[r * LT + (d - N)]; };
+    if (wave > 0) {
+#pragma unroll
+        for (int u = 0; u < NQ; ++u) {
+            const int idx = (g - 64) + NTS * u;
+            if (idx < N * N) Rd[(idx / N) * LR + idx % N] = q_aa[u];
+        }
+    }
+    constexpr int QT = (TM * TC + WPU - 1) / WPU;  // T_I tiles per wavefront
+    constexpr int KN = N / 4;                      // K steps over n
+    mf_d4 tacc[QT];
+#pragma unroll
+    for (int u = 0; u < QT; ++u) {
+        tacc[u] = mf_d4{0.0, 0.0, 0.0, 0.0};
+        const int q = wave + WPU * u;
+        if (q < TM * TC) {
+            const int ti = q % TM, tj = q / TM;
+            const int r = 16 * ti + lr, cb = 16 * tj + lr;
+            for (int kk = 4 * ti; kk < KN; ++kk) {
+                const int k = 4 * kk + lk;
+                const double av = r < N ? RI[r * LR + k] : 0.0;
+                const double bv = cb < 2 * N ? TX(k, cb) : 0.0;
+                tacc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, tacc[u], 0, 0, 0);
+            }
+        }
+    }
+    rec_sync<WPU>();  // the R part is no longer read: T_I takes its place
+#pragma unroll
+    for (int u = 0; u < QT; ++u) {
+        const int q = wave + WPU * u;
+        if (q < TM * TC) {
+            const int ti = q % TM, tj = q / TM;
+            const int cb = 16 * tj + lr;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int r = 16 * ti + lk + 4 * e;
+                if (r < N && cb < 2 * N) TT[r * LT + (cb < N ? N + 1 + cb : cb - N)] = tacc[u][e];
+            }
+        }
+    }
+    rec_sync<WPU>();
+
+    // P^T column tile ti = wave: three passes over the neighbour blocks
+    const int ti = wave;
+    const bool own = ti < TM;
+    const int c = 16 * ti + lr;  // the row of T_I this lane's B operand reads
+    mf_d4 pt[TC];
+#pragma unroll
+    for (int tk = 0; tk < TC; ++tk) pt[tk] = mf_d4{0.0, 0.0, 0.0, 0.0};
+    // pass Q: S_aa (Q = 0), S_ab (1), S_bb (2) in region 0, S_ab as S_ab(x, y) at x LR + y
+    auto pass = [&](auto qc) {
+        constexpr int Q = decltype(qc)::value;
+        if (!own) return;
+#pragma unroll
+        for (int kk = 0; kk < 2 * KN; ++kk) {
+            const bool dlo = kk < KN;  // d = 4 kk + lk < n
+            const int d = 4 * kk + lk;
+            const double bv = c < N ? TX(c, d) : 0.0;
+#pragma unroll
+            for (int tk = 0; tk < TC; ++tk) {
+                const bool plo = 16 * tk < N, phi = 16 * tk + 15 >= N;  // tile has rows p < n / p >= n
+                const bool run = Q == 0 ? (plo && dlo) : Q == 1 ? ((plo && !dlo) || (phi && dlo)) : (phi && !dlo);
+                if (!run) continue;
+                const int p = 16 * tk + lr;
+                double av;
+                if constexpr (Q == 0) {
+                    av = p < N ? Rd[p * LR + d] : 0.0;
+                } else if constexpr (Q == 1) {
+                    av = p < N ? (dlo ? 0.0 : Rd[p * LR + (d - N)])
+                               : (p < 2 * N && dlo ? Rd[d * LR + (p - N)] : 0.0);
+                } else {
+                    av = (p >= N && p < 2 * N) ? Rd[(p - N) * LR + (d - N)] : 0.0;
+                }
+                pt[tk] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, pt[tk], 0, 0, 0);
+            }
+        }
+    };
+    pass(std::integral_constant<int, 0>{});
+    rec_sync<WPU>();
+    if (wave > 0) {
+        // S_ab(rr, cc) into [rr][cc] (stored as S+ of a, or as S- of b, transposed)
+#pragma unroll
+        for (int u = 0; u < NQ; ++u) {
+            const int idx = (g - 64) + NTS * u;
+            if (idx < N * N) {
+                const int rr = idx / N, cc = idx - rr * N;
+                Rd[trans ? cc * LR + rr : rr * LR + cc] = q_ab[u];
+            }
+        }
+    }
+    rec_sync<WPU>();
+    pass(std::integral_constant<int, 1>{});
+    rec_sync<WPU>();
+    if (wave > 0) {
+#pragma unroll
+        for (int u = 0; u < NQ; ++u) {
+            const int idx = (g - 64) + NTS * u;
+            if (idx < N * N) Rd[(idx / N) * LR + idx % N] = q_bb[u];
+        }
+    }
+    rec_sync<WPU>();
+    pass(std::integral_constant<int, 2>{});
+
+    mf_d4 sc[TM];
+    if (own) {
+        // pt[tk][e] = P(c, 16 tk + lk + 4 e): -P into the S blocks / lag-one blocks
+#pragma unroll
+        for (int tk = 0; tk < TC; ++tk) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int cc = 16 * tk + lk + 4 * e;
+                if (c < N && cc < 2 * N) {
+                    const double v = pt[tk][e];
+                    if (valid && store_s) {
+                        const int64_t ri = a.rec_off[l] + t - a.spm_first;
+                        double *dst = a.spm + ri * 2 * N * N + (cc < N ? 0 : N * N);
+                        dst[c * N + (cc < N ? cc : cc - N)] = -v;
+                    }
+                    // level 0: S_{i,i+1} = -P_b, and S_{i-1,i} = S_{i,i-1}^T = -P_a^T
+                    if (l == 0 && a.lag1 && (cc < N ? va : vb)) {
+                        if (cc >= N) a.lag1[i * N * N + c * N + (cc - N)] = -v;
+                        else a.lag1[(i - 1) * N * N + cc * N + c] = -v;
+                    }
+                }
+            }
+        }
+        // S_ii row tile ti: RI RI^T over k < n, then P T_I^T over d < 2n with P from pt
+#pragma unroll
+        for (int tj = 0; tj < TM; ++tj) sc[tj] = mf_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+        for (int kk = 0; kk < KN; ++kk) {
+            const int k = 4 * kk + lk;
+            const double av = c < N ? RI[c * LR + k] : 0.0;
+#pragma unroll
+            for (int tj = 0; tj < TM; ++tj) {
+                const int cb = 16 * tj + lr;
+                const double bv = cb < N ? RI[cb * LR + k] : 0.0;
+                sc[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, sc[tj], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int kk = 0; kk < 4 * TC; ++kk) {
+            const int d = 4 * kk + lk;
+            const double av = pt[kk / 4][kk % 4];
+#pragma unroll
+            for (int tj = 0; tj < TM; ++tj) {
+                const int cb = 16 * tj + lr;
+                const double bv = (cb < N && d < 2 * N) ? TX(cb, d) : 0.0;
+                sc[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, sc[tj], 0, 0, 0);
+            }
+        }
+    }
+    rec_sync<WPU>();  // S_bb no longer read: region 0 takes S_ii
+    if (own) {
+#pragma unroll
+        for (int tj = 0; tj < TM; ++tj) {
+            const int cb = 16 * tj + lr;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int r = 16 * ti + lk + 4 * e;
+                if (r < N && cb < N) Rd[r * LR + cb] = sc[tj][e];
+            }
+        }
+    }
+    rec_sync<WPU>();
+    if (valid) {
+        for (int idx = g; idx < N * N; idx += NT) {
+            const int r = idx / N, cc = idx - r * N;
+            a.cov[i * N * N + idx] = 0.5 * (Rd[r * LR + cc] + Rd[cc * LR + r]);
+        }
+    }
+    rec_sync<WPU>();
+}
+
+template <int N, bool DO_Y, bool DO_COV, class TR, int RPW = blk_rpw(N)>
+__device__ __forceinline__ void blk_bwd_unit(const BwdArgs &a, int l, int64_t t, int64_t units, bool store_s,
+                                             double *sm) {
+    if constexpr (blk_bf(N))
+        blk_bwd_unit_bf<N, DO_Y, DO_COV, TR, RPW>(a, l, t, units, store_s, sm);
+    else
+        blk_bwd_unit_lds<N, DO_Y, DO_COV, TR, RPW>(a, l, t, units, store_s, sm);
+}
+
 template <int N, bool DO_Y, bool DO_COV, class TR, bool BATCH, int RPW>
-__global__ __launch_bounds__(256) void k_blk_backward(BwdArgs a0, const BwdArgs *tab, BlockMap bm) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(blk_min_waves<N, DO_COV>()))) void
+k_blk_backward(BwdArgs a0, const BwdArgs *tab, BlockMap bm) {
     const BwdArgs &a = BATCH ? tab[bm.item[blockIdx.x]] : a0;
     using BG = BGeo<N, RPW>;
-    constexpr int PER = BSmem<N, DO_COV>::PER;
+    constexpr int PER = blk_per<N, DO_COV>();
     __shared__ double sm[BG::RPW * PER];
     const int l = BATCH ? bm.level[blockIdx.x] : a.level;
     const int64_t blk = BATCH ? bm.blk[blockIdx.x] : (int64_t)blockIdx.x;
@@ -340,7 +709,7 @@ template <int N, bool DO_Y, bool DO_COV, bool BATCH, int RPW>
 __global__ __launch_bounds__(256) void k_blk_bwd_tail(BwdArgs a0, const BwdArgs *tab, BlockMap bm) {
     const BwdArgs &a = BATCH ? tab[bm.item[blockIdx.x]] : a0;
     using BG = BGeo<N, RPW>;
-    constexpr int PER = BSmem<N, DO_COV>::PER;
+    constexpr int PER = blk_per<N, DO_COV>();
     __shared__ double sm[BG::RPW * PER];
     const int u = threadIdx.x / BG::UT;
     for (int l = a.level; l >= a.l_lo; --l) {
@@ -361,7 +730,7 @@ __global__ __launch_bounds__(256) void k_blk_bwd_tail(BwdArgs a0, const BwdArgs 
 template <int N, bool DO_Y, bool DO_COV, class TR, int RPW>
 __global__ __launch_bounds__(256) void k_blk_bwd_multi(BwdArgs a) {
     using BG = BGeo<N, RPW>;
-    constexpr int PER = BSmem<N, DO_COV>::PER;
+    constexpr int PER = blk_per<N, DO_COV>();
     __shared__ double sm[BG::RPW * PER];
     const int u = threadIdx.x / BG::UT;
     const int64_t c = blockIdx.x;
