@@ -64,16 +64,16 @@ constexpr bool blk_bf(int n) { return n >= 24; }
 
 // LDS of one record in the blocked form (doubles): region 0 holds R_ii, then
 // the neighbour block in use (S_aa, S_ab, S_bb in turn), then S_ii; then
-// [R_i,b | rho | R_i,a] (later [T_b | . | T_a]), RI = R_ii^{-1} (covariances
-// only), and 1 / R_ii(r, r), y_a, y_b
+// [R_i,b | rho | R_i,a] (later [T_b | . | T_a]), RI = R_ii^{-1}, and
+// 1 / R_ii(r, r), y_a, y_b, w = rho - R_i,a y_a - R_i,b y_b
 template <int N, bool COV>
 struct BFSmem {
     static constexpr int LR = N + 1;
     static constexpr int LT = 2 * N + 1;
     static constexpr int TO = N * LR;
     static constexpr int IO = TO + N * LT;
-    static constexpr int DO = IO + (COV ? N * LR : 0);
-    static constexpr int PER = DO + 3 * N;
+    static constexpr int DO = IO + N * LR;
+    static constexpr int PER = DO + 4 * N;
 };
 
 template <int N, bool COV>
@@ -362,16 +362,17 @@ __device__ __forceinline__ double blk_readlane(double v, int lane) {
     return __longlong_as_double((hi << 32) | lo);
 }
 
-// One block row in the blocked form (n >= 24, two or more wavefronts per
-// record, n <= 64):
-//  1. wavefront 0: RI = R_ii^{-1} by column-oriented substitution (lane g
-//     holds column g); meanwhile the state y_i = R_ii^{-1} (rho_i - R_i,a y_a
-//     - R_i,b y_b) (a matrix-vector product, then one right-hand side by
-//     substitution with the pivot broadcast from its lane) on wavefront 1 --
-//     wavefront 0 when covariances are not wanted, which then skip every step
-//     below -- and the other wavefronts fetch S_aa, S_ab, S_bb.
-//  2. T_I = RI [R_i,a | R_i,b] on MFMA (RI upper triangular: K from 16 ti),
-//     written over the R part of the row.
+// One block row in the blocked form (24 <= n <= 48, two or more wavefronts
+// per record):
+//  1. RI = R_ii^{-1} blocked by 16 (the recurrence of LAPACK's blocked
+//     triangular inverse): wavefront 0 inverts the diagonal blocks by
+//     substitution (lane 16 b + j: column j of block b), then the blocks above
+//     them come from MFMA products, X_01 = -A^{-1} B D^{-1},
+//     X_12 = -D^{-1} E F^{-1}, X_02 = -A^{-1} (B X_12 + C F^{-1}) for
+//     R_ii = [A B C; 0 D E; 0 0 F].  Meanwhile wavefront 1 forms
+//     w = rho_i - R_i,a y_a - R_i,b y_b and the others fetch S_aa, S_ab, S_bb;
+//     then y_i = RI w.  A states-only pass stops there.
+//  2. T_I = RI [R_i,a | R_i,b] on MFMA, written over the R part of the row.
 //  3. P^T = S_II T_I^T: wavefront ti owns row tile ti of S_ii and forms the
 //     column tiles (tk, ti) of P^T, with the operand S_II read from LDS in
 //     three passes (S_aa, then S_ab, then S_bb in region 0; each tile takes
@@ -392,7 +393,7 @@ __device__ __forceinline__ void blk_bwd_unit_bf(const BwdArgs &a, int l, int64_t
     constexpr int WPU = BG::WPU;
     constexpr int TM = (N + 15) / 16;      // row tiles of S_ii, T_I; column tiles of P^T
     constexpr int TC = (2 * N + 15) / 16;  // column tiles of T_I, row tiles of P^T
-    static_assert(WPU >= 2 && WPU >= TM && N <= 64 && N % 4 == 0, "blocked form: record shape");
+    static_assert(WPU >= 2 && WPU >= TM && N <= 48 && N % 4 == 0, "blocked form: record shape");
     double *Rd = sm;  // R_ii; then S_aa, S_ab, S_bb in turn; then S_ii
     double *TT = sm + SM::TO;
     double *RI = sm + SM::IO;
@@ -454,20 +455,30 @@ __device__ __forceinline__ void blk_bwd_unit_bf(const BwdArgs &a, int l, int64_t
             }
         }
     }
-    if (DO_COV && wave == 0) {
-        if (lane < N) {
-            double x[N];
+    double *WV = DI + 3 * N;
+    constexpr int NB = (N + 15) / 16;  // diagonal blocks of R_ii
+    if (wave == 0) {
+        // the diagonal blocks' inverses; rows and columns >= n (a last block
+        // narrower than 16) are skipped through selects
+        const int o = 16 * (lane >> 4), j = lane & 15;
+        if (lane < 16 * NB && o + j < N) {
+            double x[16];
 #pragma unroll
-            for (int r = 0; r < N; ++r) x[r] = r == lane ? 1.0 : 0.0;
+            for (int r = 0; r < 16; ++r) x[r] = r == j ? 1.0 : 0.0;
 #pragma unroll
-            for (int r = N - 1; r >= 0; --r) {
-                const double xr = x[r] * DI[r];
+            for (int r = 15; r >= 0; --r) {
+                const bool rin = o + r < N;
+                const double xr = rin ? x[r] * DI[o + r] : 0.0;
                 x[r] = xr;
 #pragma unroll
-                for (int s = 0; s < r; ++s) x[s] = fma(-Rd[s * LR + r], xr, x[s]);
+                for (int s2 = 0; s2 < r; ++s2) {
+                    const double rv = rin ? Rd[(o + s2) * LR + o + r] : 0.0;
+                    x[s2] = fma(-rv, xr, x[s2]);
+                }
             }
 #pragma unroll
-            for (int r = 0; r < N; ++r) RI[r * LR + lane] = x[r];
+            for (int r = 0; r < 16; ++r)
+                if (o + r < N) RI[(o + r) * LR + o + j] = x[r];
         }
     } else {
         if constexpr (DO_COV) {
@@ -480,32 +491,101 @@ __device__ __forceinline__ void blk_bwd_unit_bf(const BwdArgs &a, int l, int64_t
                 q_bb[u] = (in && vb) ? a.cov[bb * N * N + idx] : 0.0;
             }
         }
-        if (DO_Y && wave == (DO_COV ? 1 : 0)) {
-            // w = rho - R_i,a y_a - R_i,b y_b (lane g: row g), then R_ii y = w
-            double w = 0.0;
-            if (lane < N) {
-                w = TT[lane * LT + N];
+        if (wave == 1) {
+            if (DO_Y && lane < N) {
+                // w = rho - R_i,a y_a - R_i,b y_b (lane g: row g)
+                double w = TT[lane * LT + N];
 #pragma unroll 8
                 for (int d = 0; d < N; ++d) {
                     w = fma(-TT[lane * LT + N + 1 + d], DI[N + d], w);
                     w = fma(-TT[lane * LT + d], DI[2 * N + d], w);
                 }
+                WV[lane] = w;
             }
-            double yg = 0.0;
-#pragma unroll
-            for (int r = N - 1; r >= 0; --r) {
-                const double yr = blk_readlane(w, r) * DI[r];
-                if (lane == r) yg = yr;
-                if (lane < r) w = fma(-Rd[lane * LR + r], yr, w);
-            }
-            if (valid && lane < N) a.u_out[i * N + lane] = yg;
         }
+        if (wave == WPU - 1) {
+            // RI is upper triangular: zero the blocks below the diagonal ones
+            for (int idx = lane; idx < N * N; idx += 64) {
+                const int r = idx / N, c = idx - r * N;
+                if ((r >> 4) > (c >> 4)) RI[r * LR + c] = 0.0;
+            }
+        }
+    }
+    rec_sync<WPU>();
+    // the blocks above the diagonal: X_01 on wavefront 1, X_12 then X_02 on
+    // wavefront 2 (1 when the record has two).  In each chain the first product
+    // is formed transposed, so that its result layout is the next product's
+    // operand layout.
+    {
+        // RI(o1 + r, o2 + c) = -(inv(o1) R(o1 : , o2 : ) inv(o2))(r, c) into
+        // registers (result layout) and LDS
+        auto x_above = [&](int o1, int o2) -> mf_d4 {
+            mf_d4 t1 = mf_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const int k = 4 * kk + lk;
+                const bool in = o2 + lr < N && o1 + k < N;
+                const double av = in ? Rd[(o1 + k) * LR + o2 + lr] : 0.0;  // R(o1 + k, o2 + lr)
+                const bool bin = o1 + k < N && o1 + lr < N;
+                const double bv = bin ? RI[(o1 + lr) * LR + o1 + k] : 0.0;  // inv(o1)(lr, k)
+                t1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, t1, 0, 0, 0);
+            }
+            // t1[e] = (inv(o1) R_12)(lr, lk + 4 e)
+            mf_d4 x = mf_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                const int k = 4 * kk + lk;
+                const bool in = o2 + k < N && o2 + lr < N;
+                const double bv = in ? RI[(o2 + k) * LR + o2 + lr] : 0.0;  // inv(o2)(k, lr)
+                x = __builtin_amdgcn_mfma_f64_16x16x4f64(t1[kk], bv, x, 0, 0, 0);
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                x[e] = -x[e];
+                if (o2 + lr < N) RI[(o1 + lk + 4 * e) * LR + o2 + lr] = x[e];
+            }
+            return x;
+        };
+        if (NB >= 2 && wave == 1) (void)x_above(0, 16);
+        if constexpr (NB == 3) {
+            if (wave == (WPU >= 3 ? 2 : 1)) {
+                const mf_d4 x12 = x_above(16, 32);
+                // Z = R_01 X_12 + R_02 inv(2), then X_02 = -inv(0) Z
+                mf_d4 z = mf_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    const int k = 4 * kk + lk;
+                    z = __builtin_amdgcn_mfma_f64_16x16x4f64(Rd[lr * LR + 16 + k], x12[kk], z, 0, 0, 0);
+                }
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    const int k = 4 * kk + lk;
+                    z = __builtin_amdgcn_mfma_f64_16x16x4f64(Rd[lr * LR + 32 + k], RI[(32 + k) * LR + 32 + lr], z, 0,
+                                                              0, 0);
+                }
+                mf_d4 x02 = mf_d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk) {
+                    const int k = 4 * kk + lk;
+                    x02 = __builtin_amdgcn_mfma_f64_16x16x4f64(RI[lr * LR + k], z[kk], x02, 0, 0, 0);
+                }
+#pragma unroll
+                for (int e = 0; e < 4; ++e) RI[(lk + 4 * e) * LR + 32 + lr] = -x02[e];
+            }
+        }
+    }
+    rec_sync<WPU>();  // RI complete; R_ii no longer read: region 0 takes S_aa
+    if (DO_Y && wave == WPU - 1 && lane < N) {
+        // y_i = RI w
+        double y = 0.0;
+#pragma unroll 8
+        for (int k = 0; k < N; ++k) y = fma(RI[lane * LR + k], WV[k], y);
+        if (valid) a.u_out[i * N + lane] = y;
     }
     if constexpr (!DO_COV) {
         rec_sync<WPU>();
         return;
     }
-    rec_sync<WPU>();  // RI complete; R_ii no longer read: region 0 takes S_aa
 
     // T_I(r, d) = [T_a | T_b](r, d) in [T_b | . | T_a] (same place as the R part)
     auto TX = [&](int r, int d) -> double { return d < N ? TT[r * LT + N + 1 + d] : TT[r * LT + (d - N)]; };
@@ -526,7 +606,8 @@ __device__ __forceinline__ void blk_bwd_unit_bf(const BwdArgs &a, int l, int64_t
         if (q < TM * TC) {
             const int ti = q % TM, tj = q / TM;
             const int r = 16 * ti + lr, cb = 16 * tj + lr;
-            for (int kk = 4 * ti; kk < KN; ++kk) {
+#pragma unroll
+            for (int kk = 0; kk < KN; ++kk) {  // RI(r, k) = 0 for k < 16 ti
                 const int k = 4 * kk + lk;
                 const double av = r < N ? RI[r * LR + k] : 0.0;
                 const double bv = cb < 2 * N ? TX(k, cb) : 0.0;
