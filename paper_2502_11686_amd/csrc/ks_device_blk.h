@@ -54,13 +54,13 @@ struct BSmem {
     static constexpr int PER = DO + 3 * N;           // 1 / R_ii(r, r), y_a, y_b
 };
 
-// From n = 24 on, a record runs in the blocked form (blk_bwd_unit_bf): one
+// From n = 32 on, a record runs in the blocked form (blk_bwd_unit_bf): one
 // wavefront forms R_ii^{-1} by substitution while another solves for the
 // state, T_I comes from an MFMA product with R_ii^{-1}, the neighbours'
 // covariance blocks pass through LDS one block at a time, and P stays in
 // registers between its two products.  A record then needs 76 KB of LDS at
 // n = 48 (151 KB in the form above), so two records share a CU.
-constexpr bool blk_bf(int n) { return n >= 24; }
+constexpr bool blk_bf(int n) { return n >= 32; }  // n = 24: measured 2x slower than the LDS form
 
 // LDS of one record in the blocked form (doubles): region 0 holds R_ii, then
 // the neighbour block in use (S_aa, S_ab, S_bb in turn), then S_ii; then
@@ -362,7 +362,7 @@ __device__ __forceinline__ double blk_readlane(double v, int lane) {
     return __longlong_as_double((hi << 32) | lo);
 }
 
-// One block row in the blocked form (24 <= n <= 48, two or more wavefronts
+// One block row in the blocked form (32 <= n <= 48, two or more wavefronts
 // per record):
 //  1. RI = R_ii^{-1} blocked by 16 (the recurrence of LAPACK's blocked
 //     triangular inverse): wavefront 0 inverts the diagonal blocks by

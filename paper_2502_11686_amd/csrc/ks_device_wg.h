@@ -512,6 +512,88 @@ __device__ __forceinline__ void wg_fold_part(const FwdArgs &a, int64_t t, WStack
     wg_qr<N, 2 * N, 0, 0, N, T>(X, L, vbuf, ph);
 }
 
+// The fold split across two workgroups of the level launch: the last
+// column's R row and Z rows (they depend on no unit of the level) ...
+template <int N, int MM, bool RAW, class T, class TIN>
+__device__ __forceinline__ void wg_fold_pre(const FwdArgs &a, int64_t t, T *vbuf, double &dmin, double &dmax,
+                                            bool &bad, bool &nonfinite) {
+    using G = WGeo<N, T>;
+    constexpr int RO = RAW ? MM : N;
+    constexpr int P1 = RO < N ? RO : N;
+    const WLane<N> L;
+    int ph = 0;
+    const int64_t jl = a.Nl - 1;
+    T X[4][G::RPT];
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int i = 0; i < G::RPT; ++i) X[s][i] = T(0);
+    wg_load_obs<N, MM, RAW, 0, 1, T, TIN>(X, L, a, jl);
+    if constexpr (RAW)
+        wg_whiten<N, MM, 0, 0x3, T>(a.C_diag, X, L, a.C + jl * (int64_t)(a.C_diag ? a.m : a.m * a.m), a.m,
+                                    vbuf, ph, bad);
+    wg_qr<N, RO, P1, 0x3, 0, T>(X, L, vbuf, ph);
+#pragma unroll
+    for (int i = 0; i < G::HALF; ++i) {
+        X[0][G::HALF + i] = X[0][i];
+        X[1][G::HALF + i] = X[1][i];
+        X[0][i] = X[1][i] = T(0);
+    }
+    wg_load_evol<N, RAW, 0, 2, 0, T, TIN>(X, L, a, jl);
+    if constexpr (RAW)
+        wg_whiten<N, N, 0, 0x7, T>(a.K_diag, X, L, a.K + (jl - 1) * (int64_t)(a.K_diag ? N : N * N), N, vbuf,
+                                   ph, bad);
+    wg_qr<N, 2 * N, N, 0x7, 0, T>(X, L, vbuf, ph);
+    wg_store_rrow<N, T>(slot<T>(a.rrows, t + 1, G::RREC), X, L);
+    wg_diag_stats<N, T>(X, L, dmin, dmax, nonfinite);
+    // Z (slot 2) and zeta (slot 1 of group n), rows [n, 2n): row r at r (n + 1)
+    T *z = reinterpret_cast<T *>(a.fold_z);
+#pragma unroll
+    for (int i = G::HALF; i < G::RPT; ++i) {
+        const int r = L.tr + G::TR * (i - G::HALF);
+        if (L.c <= N) z[r * (N + 1) + L.c] = L.c < N ? X[2][i] : X[1][i];
+    }
+}
+
+// ... and the merge: each of the two workgroups, done with its part, counts
+// its arrival; the second stacks Z under the last unit's step-3 triangle O'
+// (as stored) and folds it in by one more QR, then resets the counter.  No
+// workgroup waits for the other.
+template <int N, class T>
+__device__ __forceinline__ void wg_fold_join(const FwdArgs &a, int64_t t, T *vbuf) {
+    using G = WGeo<N, T>;
+    __shared__ unsigned arrival;
+    __threadfence();  // this workgroup's records are visible device-wide before it counts
+    __syncthreads();
+    if (threadIdx.x == 0) arrival = atomicAdd(a.fold_cnt, 1u);
+    __syncthreads();
+    if (arrival != 1u) return;
+    __threadfence();  // the other workgroup's records are seen
+    const WLane<N> L;
+    int ph = 0;
+    T X[4][G::RPT];
+#pragma unroll
+    for (int s = 0; s < 3; ++s)
+#pragma unroll
+        for (int i = 0; i < G::RPT; ++i) X[s][i] = T(0);
+    T *ob = slot<T>(a.sys_out, t, G::SREC);
+    const T *z = reinterpret_cast<const T *>(a.fold_z);
+#pragma unroll
+    for (int i = 0; i < G::RPT; ++i) {
+        const int r = L.tr + G::TR * (i < G::HALF ? i : i - G::HALF);
+        X[3][i] = L.c <= N ? (i < G::HALF ? ob[r * (N + 1) + L.c] : z[r * (N + 1) + L.c]) : T(0);
+    }
+    wg_qr<N, 2 * N, 0, 0, N, T>(X, L, vbuf, ph);
+#pragma unroll
+    for (int i = 0; i < G::HALF; ++i) {
+        const int r = L.tr + G::TR * i;
+        if (L.c <= N) ob[r * (N + 1) + L.c] = X[3][i];
+    }
+    if (threadIdx.x == 0) *a.fold_cnt = 0u;
+}
+
+// INLINE_FOLD: the last unit of an odd level also folds the last column in
+// (the tail kernel, one workgroup per level)
 template <int N, int MM, bool RAW, bool INLINE_FOLD, class T, class TIN>
 __device__ __forceinline__ void wg_fwd_unit(const FwdArgs &a, int64_t t, T *vbuf, double &dmin, double &dmax,
                                             bool &bad, bool &nonfinite) {
@@ -603,29 +685,43 @@ __device__ __forceinline__ void wg_fwd_unit(const FwdArgs &a, int64_t t, T *vbuf
 
 // ------------------------------------------------------------------ kernels
 
-// With FOLD, the last unit of an odd level also folds the last column in
-// (its statistics join its workgroup's slot; the level's fold slot is set
-// neutral).
+// With FOLD (an odd level of a single plan; units + 1 workgroups), workgroup
+// 0 forms the last column's R row and Z rows and writes the level's fold
+// slot, workgroups 1 .. units run the units, the last unit first, and the
+// later of workgroup 0 and the last unit's folds Z in (wg_fold_join).
 // MW: the wavefronts per SIMD the kernel is compiled for (register budget).
 template <int N, int MM, bool RAW, class T, class TIN, bool BATCH, bool FOLD = false, int MW = wg_min_waves(N)>
 __global__ __launch_bounds__(WThreads<N>::NT) __attribute__((amdgpu_waves_per_eu(MW))) void k_wg_forward(
     FwdArgs a0, const FwdArgs *tab, BlockMap bm) {
     const FwdArgs &a = BATCH ? tab[bm.item[blockIdx.x]] : a0;
-    // with FOLD the last unit (which also folds, the longest chain) is dispatched first
-    const int64_t blk = BATCH  ? bm.blk[blockIdx.x]
-                        : FOLD ? (int64_t)(gridDim.x - 1 - blockIdx.x)
-                               : (int64_t)blockIdx.x;
-    __shared__ T vbuf[4 * WGeo<N, T>::VB];
-    bool bad = false, nonfinite = false;
-    double dmin = INFINITY, dmax = 0.0;
-    wg_fwd_unit<N, MM, RAW, FOLD, T, TIN>(a, blk, vbuf, dmin, dmax, bad, nonfinite);
-    block_minmax<WGeo<N, double>::NT>(dmin, dmax, bad, nonfinite, a.flags);
-    if (threadIdx.x == 0) {
-        a.slots[2 * blk] = dmin;
-        a.slots[2 * blk + 1] = dmax;
-        if (FOLD && (a.Nl & 1) && blk == a.units - 1) {
-            a.fold_slot[0] = INFINITY;
-            a.fold_slot[1] = 0.0;
+    if constexpr (FOLD && !BATCH) {
+        __shared__ T vb[4 * WGeo<N, T>::VB];
+        bool bad = false, nonfinite = false;
+        double dmin = INFINITY, dmax = 0.0;
+        const bool pre = blockIdx.x == 0;
+        const int64_t blk = pre ? a.units - 1 : (int64_t)(gridDim.x - 1 - blockIdx.x);
+        if (pre)
+            wg_fold_pre<N, MM, RAW, T, TIN>(a, blk, vb, dmin, dmax, bad, nonfinite);
+        else
+            wg_fwd_unit<N, MM, RAW, false, T, TIN>(a, blk, vb, dmin, dmax, bad, nonfinite);
+        block_minmax<WGeo<N, double>::NT>(dmin, dmax, bad, nonfinite, a.flags);
+        if (threadIdx.x == 0) {
+            double *dst = pre ? a.fold_slot : a.slots + 2 * blk;
+            dst[0] = dmin;
+            dst[1] = dmax;
+        }
+        if (blk == a.units - 1) wg_fold_join<N, T>(a, blk, vb);
+    } else {
+        static_assert(!FOLD, "the batched launches fold in a kernel of their own");
+        const int64_t blk = BATCH ? bm.blk[blockIdx.x] : (int64_t)blockIdx.x;
+        __shared__ T vbuf[4 * WGeo<N, T>::VB];
+        bool bad = false, nonfinite = false;
+        double dmin = INFINITY, dmax = 0.0;
+        wg_fwd_unit<N, MM, RAW, false, T, TIN>(a, blk, vbuf, dmin, dmax, bad, nonfinite);
+        block_minmax<WGeo<N, double>::NT>(dmin, dmax, bad, nonfinite, a.flags);
+        if (threadIdx.x == 0) {
+            a.slots[2 * blk] = dmin;
+            a.slots[2 * blk + 1] = dmax;
         }
     }
 }
@@ -721,7 +817,7 @@ static void launch_wg_fwd_t(const FwdArgs &a, hipStream_t s) {
 }
 template <int N, int MM, class T, class TIN, int MW = wg_min_waves(N)>
 static void launch_wg_fwd_fold_t(const FwdArgs &a, hipStream_t s) {
-    hipLaunchKernelGGL((k_wg_forward<N, MM, false, T, TIN, false, true, MW>), dim3((unsigned)a.units),
+    hipLaunchKernelGGL((k_wg_forward<N, MM, false, T, TIN, false, true, MW>), dim3((unsigned)a.units + 1u),
                        dim3(WGeo<N, double>::NT), 0, s, a, nullptr, BlockMap{});
 }
 template <int N, int MM, bool RAW, class T, class TIN, int MW = wg_min_waves(N)>

@@ -107,7 +107,7 @@ const KernelSet *find_kernels(int n, int m, int fv, int bv) {
 }
 
 __global__ void k_clear_flags(unsigned *flags) {
-    if (threadIdx.x == 0) flags[0] = 0u;
+    if (threadIdx.x < kStatusWords) flags[threadIdx.x] = 0u;
 }
 
 void launch_clear_flags(unsigned *flags, hipStream_t s) {

@@ -22,6 +22,11 @@ constexpr int kMaxLevels = 64;
 
 // Arguments of one forward level (odd-even elimination of the even block
 // columns of the level-l system, Section III).
+// a plan's status words (64 bytes): [0] the flags, [kFoldCounter] the fold
+// arrival counter; all cleared at the start of every pass
+constexpr int kStatusWords = 16;
+constexpr int kFoldCounter = 8;
+
 struct FwdArgs {
     int64_t k;        // evolution steps of the problem
     int64_t Nl;       // block columns in this level's system
@@ -38,6 +43,11 @@ struct FwdArgs {
     double *slots;    // per-block [min |R_pp|, max |R_pp|]
     double *fold_slot;  // [min, max] of the level's fold kernel
     unsigned *flags;
+    // the fold split across two workgroups of a level launch (single plans):
+    // Z rows of the last column (n x (n+1) of the level's record type) and
+    // the arrival counter of the two workgroups (zero between launches)
+    double *fold_z;
+    unsigned *fold_cnt;
     // first column (observation step, reduced-system record) and first
     // evolution entry that the input pointers above start at: 0 for the
     // caller's arrays; nonzero when a kernel reads a staged copy of a slice

@@ -86,7 +86,7 @@ struct Layout {
     int64_t nslots;
     int64_t spm_first;                 // first record with stored S blocks (level 1)
     int64_t spm_records;
-    size_t off_rrows, off_sys, off_spm, off_slots, off_obj, off_flags, total;
+    size_t off_rrows, off_sys, off_spm, off_slots, off_obj, off_flags, off_foldz, total;
 };
 
 bool valid_desc(const ks_desc *d) {
@@ -143,6 +143,8 @@ bool make_layout(const ks_desc *d, const ks::KernelSet *ks_, Layout *lo) {
     off = align_up(off + sizeof(double) * (size_t)(ks::kObjBlocks + 1));
     lo->off_flags = off;
     off = align_up(off + 64);
+    lo->off_foldz = off;
+    off = align_up(off + sizeof(double) * (size_t)(n * (n + 1)));
     lo->total = off;
     return true;
 }
@@ -404,6 +406,8 @@ void enqueue_forward(ks_plan *p, const double *H, const double *F, const double 
     a.C_diag = p->d.C_layout == KS_COV_DIAG;
     a.H = H; a.F = F; a.c = c; a.K = K; a.G = G; a.o = o; a.C = C;
     a.flags = flags;
+    a.fold_z = seg_d(p, lo.off_foldz);
+    a.fold_cnt = flags + ks::kFoldCounter;
     const int head_end = l0 >= 1 ? fwd_launch_end(p, 0) : 0;
     const int l_first = part == 2 ? head_end : 0, l_end = part == 1 ? head_end : l0;
     for (int l = l_first; l < l_end;) {
