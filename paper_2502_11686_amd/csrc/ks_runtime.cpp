@@ -228,6 +228,8 @@ struct ks_plan {
     Layout lo;
     bool smoothed;
     unsigned host_flags;   // status word copied back after each call
+    unsigned *pinned_flags;  // the same in pinned host memory (plans from ks_create; nullptr otherwise):
+                             // a copy into it completes without the pageable staging round trip
     int l_switch;          // FP32 form: levels below this one run in FP32 (0 = none)
     int l0;                // first level of the forward tail launch
     int l1[3];             // lowest level of the backward tail launch, per backward mode
@@ -539,12 +541,13 @@ ks_status finish(ks_plan *p) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return KS_E_HIP;
     const unsigned *flags = reinterpret_cast<const unsigned *>(p->ws + p->lo.off_flags);
-    e = hipMemcpyAsync(&p->host_flags, flags, sizeof(unsigned), hipMemcpyDeviceToHost, p->stream);
+    unsigned *dst = p->pinned_flags ? p->pinned_flags : &p->host_flags;
+    e = hipMemcpyAsync(dst, flags, sizeof(unsigned), hipMemcpyDeviceToHost, p->stream);
     if (e != hipSuccess) return KS_E_HIP;
     e = hipStreamSynchronize(p->stream);
     if (e != hipSuccess) return KS_E_HIP;
     collect_time(p);
-    const unsigned f = p->host_flags;
+    const unsigned f = *dst;
     if (f & ks::FLAG_NOT_SPD) return KS_E_NOT_SPD;
     if (f & ks::FLAG_NONFINITE) return KS_E_NONFINITE;
     if (f & ks::FLAG_RANK) return KS_E_RANK;
@@ -631,6 +634,10 @@ ks_status ks_create(const ks_desc *desc, void *workspace, size_t ws_bytes, void 
     p->lo = lo;
     p->smoothed = false;
     p->host_flags = 0;
+    p->pinned_flags = nullptr;
+    if (hipHostMalloc(reinterpret_cast<void **>(&p->pinned_flags), sizeof(unsigned), hipHostMallocDefault) !=
+        hipSuccess)
+        p->pinned_flags = nullptr;  // the pageable word serves
     p->time_kind = KS_TIME_OFF;
     p->time_armed = false;
     p->ev_made = false;
@@ -739,6 +746,7 @@ ks_status ks_covariances(ks_plan *p, double *cov_out) {
 ks_status ks_destroy(ks_plan *p) {
     if (!p) return KS_E_ARG;
     p->graph.destroy();
+    if (p->pinned_flags) (void)hipHostFree(p->pinned_flags);
     if (p->ev_made) {
         (void)hipEventDestroy(p->ev[0]);
         (void)hipEventDestroy(p->ev[1]);
@@ -864,6 +872,7 @@ ks_status smooth_cov_on(const ks_desc *desc, void *workspace, size_t ws_bytes, h
     p.kset = kset;
     p.smoothed = false;
     p.host_flags = 0;
+    p.pinned_flags = nullptr;  // allocates nothing
     p.time_kind = KS_TIME_OFF;
     p.time_armed = false;
     p.ev_made = false;
