@@ -263,7 +263,7 @@ __device__ __forceinline__ void blk_bwd_unit_lds(const BwdArgs &a, int l, int64_
         mf_d4 acc[QP];
 #pragma unroll
         for (int u = 0; u < QP; ++u) acc[u] = mf_d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 2
+#pragma unroll
         for (int kk = 0; kk < KP; ++kk) {
             const int d = 4 * kk + lk;
 #pragma unroll
@@ -312,7 +312,7 @@ __device__ __forceinline__ void blk_bwd_unit_lds(const BwdArgs &a, int l, int64_
         mf_d4 sc[QS];
 #pragma unroll
         for (int u = 0; u < QS; ++u) sc[u] = mf_d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll 2
+#pragma unroll
         for (int kk = 0; kk < KS; ++kk) {
             const int k = 4 * kk + lk;
             const bool kin = (3 * N) % 4 == 0 || k < 3 * N;
@@ -763,6 +763,17 @@ __device__ __forceinline__ void blk_bwd_unit_bf(const BwdArgs &a, int l, int64_t
     rec_sync<WPU>();
 }
 
+// the record slot of this thread's wavefront in its workgroup; a record spans
+// whole wavefronts (UT a multiple of 64), so the value is uniform over the
+// wavefront, and read from its first lane the compiler knows it: the record's
+// indices, pointers and validity then live in scalar registers and the
+// branches on them are scalar
+template <int UT>
+__device__ __forceinline__ int blk_record_slot() {
+    static_assert(UT % 64 == 0, "a record spans whole wavefronts");
+    return __builtin_amdgcn_readfirstlane((int)(threadIdx.x / UT));
+}
+
 template <int N, bool DO_Y, bool DO_COV, class TR, int RPW = blk_rpw(N)>
 __device__ __forceinline__ void blk_bwd_unit(const BwdArgs &a, int l, int64_t t, int64_t units, bool store_s,
                                              double *sm) {
@@ -781,7 +792,7 @@ k_blk_backward(BwdArgs a0, const BwdArgs *tab, BlockMap bm) {
     __shared__ double sm[BG::RPW * PER];
     const int l = BATCH ? bm.level[blockIdx.x] : a.level;
     const int64_t blk = BATCH ? bm.blk[blockIdx.x] : (int64_t)blockIdx.x;
-    const int u = threadIdx.x / BG::UT;
+    const int u = blk_record_slot<BG::UT>();
     blk_bwd_unit<N, DO_Y, DO_COV, TR, RPW>(a, l, blk * BG::RPW + u, (a.Nl[l] + 1) / 2, a.store_s && l >= 1,
                                            sm + u * PER);
 }
@@ -792,7 +803,7 @@ __global__ __launch_bounds__(256) void k_blk_bwd_tail(BwdArgs a0, const BwdArgs 
     using BG = BGeo<N, RPW>;
     constexpr int PER = blk_per<N, DO_COV>();
     __shared__ double sm[BG::RPW * PER];
-    const int u = threadIdx.x / BG::UT;
+    const int u = blk_record_slot<BG::UT>();
     for (int l = a.level; l >= a.l_lo; --l) {
         const int64_t units = (a.Nl[l] + 1) / 2;
         for (int64_t t0 = 0; t0 < units; t0 += BG::RPW)
@@ -813,7 +824,7 @@ __global__ __launch_bounds__(256) void k_blk_bwd_multi(BwdArgs a) {
     using BG = BGeo<N, RPW>;
     constexpr int PER = blk_per<N, DO_COV>();
     __shared__ double sm[BG::RPW * PER];
-    const int u = threadIdx.x / BG::UT;
+    const int u = blk_record_slot<BG::UT>();
     const int64_t c = blockIdx.x;
     for (int l = a.level; l >= a.l_lo; --l) {
         const int64_t recs = (a.Nl[l] + 1) / 2;
