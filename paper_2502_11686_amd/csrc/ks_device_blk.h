@@ -249,7 +249,7 @@ __device__ __forceinline__ void blk_bwd_unit_lds(const BwdArgs &a, int l, int64_
         constexpr int QS = (TM * TM + WPU - 1) / WPU;  // S tiles per wavefront
         constexpr int KP = (2 * N + 3) / 4;    // K steps of P (inner index >= 2n is zero)
         constexpr int KS = (3 * N + 3) / 4;    // K steps of S_ii (inner index >= 3n is zero)
-        const int wave = g >> 6, lane = g & 63;
+        const int wave = __builtin_amdgcn_readfirstlane(g >> 6), lane = g & 63;
         const int lr = lane & 15, lk = lane >> 4;
         // S_II(d, c) for d, c < 2n (missing neighbours give zero blocks)
         auto SII = [&](int d, int c) -> double {
@@ -399,7 +399,7 @@ __device__ __forceinline__ void blk_bwd_unit_bf(const BwdArgs &a, int l, int64_t
     double *RI = sm + SM::IO;
     double *DI = sm + SM::DO;
     const int g = threadIdx.x % NT;
-    const int wave = g >> 6, lane = g & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(g >> 6), lane = g & 63;
     const int lr = lane & 15, lk = lane >> 4;
     const bool valid = t < units;
     const int64_t i = ((2 * t + 1) << l) - 1;
