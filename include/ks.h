@@ -288,7 +288,8 @@ ks_status ks_get_tuning(int32_t n, int32_t precision, ks_tuning *out);
  * 2-D tiled forward compiled for another occupancy target (n = 32 without
  * the four-wavefronts-per-SIMD register cap, n = 48 with it); backward
  * variants of the MFMA family take 4, 2 or
- * 1 records per workgroup (n <= 12; n = 16, 24: 2 or 1; n = 32: 1 or 2), and
+ * 1 records per workgroup (n <= 12; n = 16, 24: 2 or 1; n = 32: 1 or 2;
+ * n = 32 and 48 run the blocked form of that backward), and
  * for n = 1, 2, 3, 5 backward variant 1 is the MFMA family instead of the
  * wavefront family.  Host-only. */
 int32_t ks_kernel_variants(int32_t n, int32_t m, int32_t backward);
