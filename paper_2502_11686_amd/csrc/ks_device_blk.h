@@ -181,8 +181,8 @@ __device__ __forceinline__ void blk_bwd_unit_lds(const BwdArgs &a, int l, int64_
         if (idx < N * W) {
             const int r = idx / W, c = idx - r * W;
             const double v = valid ? rv[u] : (c == r ? 1.0 : 0.0);
-            if (c < N) Rd[r * LR + c] = v;
-            else TT[r * LT + (c - N)] = v;
+            // one store through a selected address (no branch per element)
+            *(c < N ? Rd + r * LR + c : TT + r * LT + (c - N)) = v;
         }
     }
     if (DO_Y && g < N) {
@@ -195,7 +195,12 @@ __device__ __forceinline__ void blk_bwd_unit_lds(const BwdArgs &a, int l, int64_
     if (g < W && (DO_COV || g >= N)) {
         double x[N];
 #pragma unroll
-        for (int r = 0; r < N; ++r) x[r] = g < N ? (r == g ? 1.0 : 0.0) : TT[r * LT + (g - N)];
+        for (int r = 0; r < N; ++r) {
+            // x = e_g (g < n) or column g - n of the R part: one read by every
+            // lane and a multiply-add (a select would become a branch per row)
+            const double tv = TT[r * LT + (g < N ? 0 : g - N)];
+            x[r] = fma(tv, g < N ? 0.0 : 1.0, r == g ? 1.0 : 0.0);
+        }
 #pragma unroll
         for (int r = N - 1; r >= 0; --r) {
             const double xr = x[r] * DI[r];
@@ -203,13 +208,10 @@ __device__ __forceinline__ void blk_bwd_unit_lds(const BwdArgs &a, int l, int64_
 #pragma unroll
             for (int s = 0; s < r; ++s) x[s] = fma(-Rd[s * LR + r], xr, x[s]);
         }
-        if (g < N) {
+        double *dst = g < N ? RI + g : TT + (g - N);
+        const int ld = g < N ? LR : LT;
 #pragma unroll
-            for (int r = 0; r < N; ++r) RI[r * LR + g] = x[r];
-        } else {
-#pragma unroll
-            for (int r = 0; r < N; ++r) TT[r * LT + (g - N)] = x[r];
-        }
+        for (int r = 0; r < N; ++r) dst[r * ld] = x[r];
     }
     if constexpr (DO_COV) {
         // S_ab(rr, cc) into SX[rr][cc] (S_ab is stored as S+ of a, or as S- of b, transposed)
@@ -300,8 +302,8 @@ __device__ __forceinline__ void blk_bwd_unit_lds(const BwdArgs &a, int l, int64_
                         }
                         // level 0: S_{i,i+1} = -P_b, and S_{i-1,i} = S_{i,i-1}^T = -P_a^T
                         if (l == 0 && a.lag1 && (c < N ? va : vb)) {
-                            if (c >= N) a.lag1[i * N * N + r * N + (c - N)] = -acc[u][j];
-                            else a.lag1[(i - 1) * N * N + c * N + r] = -acc[u][j];
+                            const int64_t off = c >= N ? i * N * N + r * N + (c - N) : (i - 1) * N * N + c * N + r;
+                            a.lag1[off] = -acc[u][j];
                         }
                     }
                 }
@@ -426,8 +428,8 @@ __device__ __forceinline__ void blk_bwd_unit_bf(const BwdArgs &a, int l, int64_t
         if (idx < N * W) {
             const int r = idx / W, c = idx - r * W;
             const double v = valid ? rv[u] : (c == r ? 1.0 : 0.0);
-            if (c < N) Rd[r * LR + c] = v;
-            else TT[r * LT + (c - N)] = v;
+            // one store through a selected address (no branch per element)
+            *(c < N ? Rd + r * LR + c : TT + r * LT + (c - N)) = v;
         }
     }
     if (DO_Y && g < N) {
