@@ -264,9 +264,15 @@ template <int N, int H, class LR, class T, class TIN>
 __device__ __forceinline__ void load_obs_sys(T (&x)[H], int roff, const TIN *obs,
                                              const LR &L, int own, bool valid, int rhs = RHS) {
     const int col = (L.role == own) ? L.rc : (L.role == rhs ? N : -1);
-    const bool ld = valid && col >= 0;
+    // one conditional region for all rows (a select per row would become a
+    // branch per row)
+    if (valid && col >= 0) {
 #pragma unroll
-    for (int r = 0; r < N; ++r) x[roff + r] = ld ? T(obs[r * (N + 1) + col]) : T(0);
+        for (int r = 0; r < N; ++r) x[roff + r] = T(obs[r * (N + 1) + col]);
+    } else {
+#pragma unroll
+        for (int r = 0; r < N; ++r) x[roff + r] = T(0);
+    }
 }
 
 // evolution block of a reduced-system column, rows [E- | E+ | eta]
@@ -277,9 +283,13 @@ __device__ __forceinline__ void load_evol_sys(T (&x)[H], int roff, const TIN *ev
     const int col = L.role == role_m ? L.rc
                   : L.role == role_p ? N + L.rc
                   : L.role == RHS    ? 2 * N : -1;
-    const bool ld = valid && col >= 0;
+    if (valid && col >= 0) {
 #pragma unroll
-    for (int r = 0; r < N; ++r) x[roff + r] = ld ? T(ev[r * (2 * N + 1) + col]) : T(0);
+        for (int r = 0; r < N; ++r) x[roff + r] = T(ev[r * (2 * N + 1) + col]);
+    } else {
+#pragma unroll
+        for (int r = 0; r < N; ++r) x[roff + r] = T(0);
+    }
 }
 
 // Raw observation step j, rows [G_j | o_j] (m rows, zero rows up to MM), and
@@ -296,20 +306,37 @@ __device__ __forceinline__ void load_obs_raw(T (&x)[H], int roff, T (&cv)[MM],
     j -= a.col0;
     const double *Gj = a.G + j * (int64_t)m * N;
     const double *oj = a.o + j * (int64_t)m;
+    // one conditional region per lane for its loads (m is uniform); the
+    // column of G or o is chosen by address
+    if (ld) {
+        const double *src = col < N ? Gj + col : oj;
+        const int stride = col < N ? N : 1;
 #pragma unroll
-    for (int r = 0; r < MM; ++r)
-        x[roff + r] = (ld && r < m) ? T(col < N ? Gj[r * N + col] : oj[r]) : T(0);
+        for (int r = 0; r < MM; ++r) x[roff + r] = r < m ? T(src[r * stride]) : T(0);
+    } else {
+#pragma unroll
+        for (int r = 0; r < MM; ++r) x[roff + r] = T(0);
+    }
     if (a.C_diag) {
         const double *Cj = a.C + j * (int64_t)m;
+        if (valid) {
 #pragma unroll
-        for (int r = 0; r < MM; ++r) cv[r] = (valid && r < m) ? T(Cj[r]) : T(1);
+            for (int r = 0; r < MM; ++r) cv[r] = r < m ? T(Cj[r]) : T(1);
+        } else {
+#pragma unroll
+            for (int r = 0; r < MM; ++r) cv[r] = T(1);
+        }
     } else {
         const double *Cj = a.C + j * (int64_t)m * m;
         const int q = gl - cl0;
         const bool mine = (unsigned)q < (unsigned)MM;
+        if (mine && valid && q < m) {
 #pragma unroll
-        for (int r = 0; r < MM; ++r)
-            cv[r] = !mine ? T(0) : (valid && q < m && r < m) ? T(Cj[r * m + q]) : T(r == q ? 1 : 0);
+            for (int r = 0; r < MM; ++r) cv[r] = r < m ? T(Cj[r * m + q]) : T(r == q ? 1 : 0);
+        } else {
+#pragma unroll
+            for (int r = 0; r < MM; ++r) cv[r] = mine ? T(r == q ? 1 : 0) : T(0);
+        }
     }
 }
 
@@ -323,27 +350,42 @@ __device__ __forceinline__ void load_evol_raw(T (&x)[H], int roff, T (&cv)[N], i
     const double *F = a.F + t * N * N;
     const double *Hm = a.H ? a.H + t * N * N : nullptr;
     const double *c = a.c + t * N;
+    // the lane's source column (-F, H or c), chosen once; one conditional
+    // region holds its loads
+    const bool fm = valid && L.role == role_m;
+    const bool fh = valid && L.role == role_p && Hm;
+    const bool fc = valid && L.role == RHS;
+    if (fm || fh || fc) {
+        const double *src = fm ? F + L.rc : fh ? Hm + L.rc : c;
+        const int stride = fc ? 1 : N;
+        const double sgn = fm ? -1.0 : 1.0;
 #pragma unroll
-    for (int r = 0; r < N; ++r) {
-        double v = 0.0;
-        if (valid) {
-            if (L.role == role_m) v = -F[r * N + L.rc];
-            else if (L.role == role_p) v = Hm ? Hm[r * N + L.rc] : (r == L.rc ? 1.0 : 0.0);
-            else if (L.role == RHS) v = c[r];
-        }
-        x[roff + r] = T(v);
+        for (int r = 0; r < N; ++r) x[roff + r] = T(sgn * src[r * stride]);
+    } else {
+        const bool ident = valid && L.role == role_p;  // H = identity
+#pragma unroll
+        for (int r = 0; r < N; ++r) x[roff + r] = T(ident && r == L.rc ? 1.0 : 0.0);
     }
     if (a.K_diag) {
         const double *Kt = a.K + t * N;
+        if (valid) {
 #pragma unroll
-        for (int r = 0; r < N; ++r) cv[r] = valid ? T(Kt[r]) : T(1);
+            for (int r = 0; r < N; ++r) cv[r] = T(Kt[r]);
+        } else {
+#pragma unroll
+            for (int r = 0; r < N; ++r) cv[r] = T(1);
+        }
     } else {
         const double *Kt = a.K + t * N * N;
         const int q = gl - cl0;
         const bool mine = (unsigned)q < (unsigned)N;
+        if (mine && valid) {
 #pragma unroll
-        for (int r = 0; r < N; ++r)
-            cv[r] = !mine ? T(0) : valid ? T(Kt[r * N + q]) : T(r == q ? 1 : 0);
+            for (int r = 0; r < N; ++r) cv[r] = T(Kt[r * N + q]);
+        } else {
+#pragma unroll
+            for (int r = 0; r < N; ++r) cv[r] = mine ? T(r == q ? 1 : 0) : T(0);
+        }
     }
 }
 
