@@ -73,8 +73,10 @@ const KernelSet *find_kernels(int n, int m, int fv, int bv) {
     if (fv == 0 && bv == 0) return d;
     const KernelSet *f = entry(n, d->mm, fv, 0), *b = entry(n, d->mm, 0, bv);
     if (!f || !b) return nullptr;
-    if (fv == 0) return b;
-    if (bv == 0) return f;
+    if (fv == 0) return b;  // a backward variant's set carries the default forward
+    // a forward variant's set need not carry the default backward (n = 4..12:
+    // the unstaged level-0 set keeps the wavefront family's backward, the
+    // default is the MFMA one), so the backward half always comes from b
     std::lock_guard<std::mutex> lock(g_compose_mu);
     auto key = std::make_tuple(n, d->mm, fv, bv);
     auto it = g_composed.find(key);
